@@ -1,0 +1,214 @@
+"""CPU oracle for the SALT hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU product path (the package
+``paper_1109_1264_amd``) never imports, links or runs anything here, and the
+two share no code: the only common module is the seeded input generator
+(``paper_1109_1264_amd.workloads``), which holds none of the method's
+arithmetic.
+
+The arithmetic lives in ``salt_oracle.c`` (plain C, built with gcc and
+``-ffp-contract=off``). This module loads it and wraps it for numpy arrays:
+
+- :func:`eval_program` -- the fused element-wise expression (paper Sec. 2,
+  Fig. 1), a per-element stack machine over the postfix tree.
+- :func:`axpy` -- ``y <- alpha*x + y`` (Sec. 5, xAXPY).
+- :func:`dot2`, :func:`nrm2` -- the root reductions (Sec. 2 "dot product or
+  norm", Sec. 4.2 reduction step), as Dot2 values (Ogita-Rump-Oishi 2005).
+- :func:`naive_dot` -- plain sequential loops (timing baseline, FP32 mode).
+
+16-bit storage arrays are ``numpy.uint16`` bit patterns; ``dtype`` names are
+``"f64"``, ``"f32"``, ``"bf16"`` and ``"f16"``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "salt_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+# Opcodes of the postfix encoding (token = (arg << 8) | opcode). The oracle
+# keeps its own copy: it shares no header with the GPU library.
+LOAD, SCALAR, ADD, SUB, MUL = 1, 2, 3, 4, 5
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+          "-fno-fast-math", "-fexcess-precision=standard"]
+
+
+def build(force: bool = True) -> str:
+    """Compile ``salt_oracle.c`` into ``liboracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded oracle library (built on first use if absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        _lib = load(_LIB_PATH)
+    return _lib
+
+
+def load(path: str) -> ctypes.CDLL:
+    """Load an oracle build from ``path`` and declare its signatures."""
+    L = ctypes.CDLL(path)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    L.oracle_eval_f64.argtypes = [P, I, P, I, P, I, P, I64]
+    L.oracle_eval_f32.argtypes = [P, I, P, I, P, I, P, I64]
+    L.oracle_eval_h16.argtypes = [I, P, I, P, I, P, I, P, I64]
+    for f in (L.oracle_eval_f64, L.oracle_eval_f32, L.oracle_eval_h16):
+        f.restype = I
+    L.oracle_axpy_f64.argtypes = [I64, D, P, P]
+    L.oracle_axpy_f32.argtypes = [I64, D, P, P]
+    L.oracle_axpy_f64.restype = L.oracle_axpy_f32.restype = I
+    L.oracle_dot2.argtypes = [I64, P, P, P, P]
+    L.oracle_dot2.restype = I
+    L.oracle_nrm2.argtypes = [I64, P, P]
+    L.oracle_nrm2.restype = I
+    L.oracle_naive_dot_f64.argtypes = [I64, P, P]
+    L.oracle_naive_dot_f64.restype = D
+    L.oracle_naive_dot_f32.argtypes = [I64, P, P]
+    L.oracle_naive_dot_f32.restype = ctypes.c_float
+    L.oracle_widen_h16.argtypes = [I, P, P, I64]
+    L.oracle_widen_h16.restype = None
+    L.oracle_narrow_h16.argtypes = [I, P, P, I64]
+    L.oracle_narrow_h16.restype = None
+    L.oracle_bf16_to_f32.argtypes = [ctypes.c_uint16]
+    L.oracle_bf16_to_f32.restype = ctypes.c_float
+    L.oracle_f32_to_bf16.argtypes = [ctypes.c_float]
+    L.oracle_f32_to_bf16.restype = ctypes.c_uint16
+    L.oracle_f16_to_f32.argtypes = [ctypes.c_uint16]
+    L.oracle_f16_to_f32.restype = ctypes.c_float
+    L.oracle_f32_to_f16.argtypes = [ctypes.c_float]
+    L.oracle_f32_to_f16.restype = ctypes.c_uint16
+    return L
+
+
+_NP = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16, "f16": np.uint16}
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _ptr_array(arrays):
+    arr = (ctypes.c_void_p * max(1, len(arrays)))()
+    for k, a in enumerate(arrays):
+        arr[k] = _ptr(a)
+    return arr
+
+
+def eval_program(prog, operands, scalars, dtype: str, n: int | None = None) -> np.ndarray:
+    """Evaluate a postfix program element by element (see module docstring).
+
+    ``operands`` are 1-D arrays of the storage type, ``scalars`` Python floats
+    (rounded once to the compute type). Returns a new array of length ``n``.
+    """
+    prog = np.ascontiguousarray(prog, dtype=np.uint32)
+    ops = [np.ascontiguousarray(a, dtype=_NP[dtype]) for a in operands]
+    if n is None:
+        n = len(ops[0]) if ops else 0
+    for a in ops:
+        if len(a) < n:
+            raise ValueError("operand shorter than n")
+    sc = np.ascontiguousarray(scalars, dtype=np.float64).reshape(-1)
+    out = np.empty(n, dtype=_NP[dtype])
+    L = lib()
+    pa = _ptr_array(ops)
+    scp = _ptr(sc) if len(sc) else None
+    if dtype == "f64":
+        rc = L.oracle_eval_f64(_ptr(prog), len(prog), pa, len(ops), scp, len(sc), _ptr(out), n)
+    elif dtype == "f32":
+        rc = L.oracle_eval_f32(_ptr(prog), len(prog), pa, len(ops), scp, len(sc), _ptr(out), n)
+    else:
+        kind = 0 if dtype == "bf16" else 1
+        rc = L.oracle_eval_h16(kind, _ptr(prog), len(prog), pa, len(ops), scp, len(sc), _ptr(out), n)
+    if rc != 0:
+        raise ValueError("oracle rejected the program or arguments")
+    return out
+
+
+def axpy(alpha: float, x: np.ndarray, y: np.ndarray, dtype: str) -> np.ndarray:
+    """Return ``alpha*x + y`` (a new array; ``y`` is not modified)."""
+    x = np.ascontiguousarray(x, dtype=_NP[dtype])
+    out = np.array(y, dtype=_NP[dtype], copy=True)
+    L = lib()
+    if dtype == "f64":
+        L.oracle_axpy_f64(len(x), float(alpha), _ptr(x), _ptr(out))
+    elif dtype == "f32":
+        L.oracle_axpy_f32(len(x), float(alpha), _ptr(x), _ptr(out))
+    else:
+        # 16-bit storage: the axpy tree through the generic 16-bit machine.
+        return eval_program([(0 << 8) | SCALAR, (0 << 8) | LOAD, MUL, (1 << 8) | LOAD, ADD],
+                            [x, out], [alpha], dtype)
+    return out
+
+
+def widen(a: np.ndarray, dtype: str) -> np.ndarray:
+    """Exact value of stored elements as float64 (16-bit storage widened)."""
+    if dtype in ("f64", "f32"):
+        return np.asarray(a, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.uint16)
+    out = np.empty(len(a), dtype=np.float64)
+    lib().oracle_widen_h16(0 if dtype == "bf16" else 1, _ptr(a), _ptr(out), len(a))
+    return out
+
+
+def narrow(values, dtype: str) -> np.ndarray:
+    """Round binary32 values to 16-bit storage with the oracle's RNE rule."""
+    f = np.ascontiguousarray(values, dtype=np.float32).reshape(-1)
+    out = np.empty(len(f), dtype=np.uint16)
+    lib().oracle_narrow_h16(0 if dtype == "bf16" else 1, _ptr(f), _ptr(out), len(f))
+    return out
+
+
+def dot2(x: np.ndarray, y: np.ndarray) -> tuple[float, float]:
+    """Dot2 value of sum x_i*y_i in binary64, and sum |x_i*y_i|.
+
+    Inputs must already be float64 (use :func:`widen` for stored values).
+    """
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    if len(x) != len(y):
+        raise ValueError("length mismatch")
+    r = ctypes.c_double()
+    a = ctypes.c_double()
+    lib().oracle_dot2(len(x), _ptr(x), _ptr(y), ctypes.byref(r), ctypes.byref(a))
+    return r.value, a.value
+
+
+def nrm2(x: np.ndarray) -> float:
+    """sqrt(Dot2(x, x)) of float64 values."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r = ctypes.c_double()
+    lib().oracle_nrm2(len(x), _ptr(x), ctypes.byref(r))
+    return r.value
+
+
+def naive_dot(x: np.ndarray, y: np.ndarray, dtype: str = "f64") -> float:
+    """Plain sequential loop in binary64 or binary32."""
+    L = lib()
+    if dtype == "f32":
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        return float(L.oracle_naive_dot_f32(len(x), _ptr(x), _ptr(y)))
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return float(L.oracle_naive_dot_f64(len(x), _ptr(x), _ptr(y)))
+
+
+# Reduction tolerances, relative to sum |x_i*y_i| of the stored values.
+TOL = {"f64": 1e-13, "f32": 1e-6, "bf16": 1e-6, "f16": 1e-6}

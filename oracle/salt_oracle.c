@@ -1,0 +1,279 @@
+/*
+ * salt_oracle.c -- plain, slow, obviously correct CPU reference for the SALT
+ * hot path (fused element-wise vector expressions, axpy, dot, nrm2).
+ *
+ * TEST INFRASTRUCTURE ONLY. The test suite, the smoke check and the
+ * benchmark's CPU-baseline leg are the only code allowed to load this
+ * library. The GPU product path never calls it, and the two share no code.
+ *
+ * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -fno-fast-math
+ *        (contraction off: every add, sub and mul is one IEEE operation).
+ *
+ * What is computed, and the passage each function follows:
+ *  - oracle_eval_*: the expression tree is evaluated lazily at assignment,
+ *    once per element, one loop over all elements (Sec. 2, Fig. 1: the tree
+ *    for d = a + (b - c); fusion keeps intermediates in registers and does not
+ *    change the per-element arithmetic). The tree arrives in postfix form; it
+ *    is run as a stack machine per element, each ADD/SUB/MUL rounded once to
+ *    the compute precision, round-to-nearest-even, no contraction.
+ *  - oracle_axpy_*: y = y + alpha*x (Sec. 5, the xAXPY benchmark), i.e. the
+ *    tree [SCALAR0 LOAD0 MUL LOAD1 ADD] written as its plain definition.
+ *  - oracle_dot2: the dot product reduction at the root of a tree (Sec. 2,
+ *    "dot product or norm"; Sec. 4.2, the reduction step). A reduction's order
+ *    is not fixed by the paper, so only the exact real value is well defined;
+ *    the oracle approximates it with Dot2 (Ogita, Rump and Oishi, "Accurate
+ *    sum and dot product", SIAM J. Sci. Comput. 26(6), 2005, Alg. 5.3), whose
+ *    error is at most u|x.y| + gamma_n^2 |x|.|y| in binary64.
+ *  - oracle_nrm2: the "norm" of Sec. 2, read as the unscaled 2-norm
+ *    sqrt(sum x_i^2), from Dot2(x, x).
+ *  - oracle_naive_dot_*: plain sequential loops, kept as a CPU timing baseline
+ *    and as the same-precision FP32 mode (not a reference value at large n).
+ *
+ * Storage types: binary64 ("f64"), binary32 ("f32"), bfloat16 and binary16
+ * held as raw 16-bit patterns. 16-bit storage is widened exactly to binary32,
+ * computed in binary32, and narrowed once with round-to-nearest-even; the
+ * widening and narrowing below are written from the formats' definitions.
+ *
+ * Program encoding: each token is a uint32 = (arg << 8) | opcode with opcodes
+ * LOAD=1 (push operand[arg][i]), SCALAR=2 (push scalars[arg] rounded once to
+ * the compute type), ADD=3, SUB=4, MUL=5 (pop r, pop l, push l op r).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#define OR_LOAD 1u
+#define OR_SCALAR 2u
+#define OR_ADD 3u
+#define OR_SUB 4u
+#define OR_MUL 5u
+#define OR_MAX_TOKENS 64
+#define OR_MAX_STACK 64
+
+/* Return codes: 0 ok, 1 bad program / argument. */
+
+/* ---- program check (the oracle's own, minimal) ---------------------------- */
+static int check_program(const uint32_t *prog, int len, int n_ops, int n_sc) {
+    if (!prog || len <= 0 || len > OR_MAX_TOKENS) return 1;
+    int depth = 0;
+    for (int t = 0; t < len; ++t) {
+        uint32_t op = prog[t] & 0xffu, arg = prog[t] >> 8;
+        if (op == OR_LOAD) {
+            if ((int)arg >= n_ops) return 1;
+            ++depth;
+        } else if (op == OR_SCALAR) {
+            if ((int)arg >= n_sc) return 1;
+            ++depth;
+        } else if (op == OR_ADD || op == OR_SUB || op == OR_MUL) {
+            if (arg != 0 || depth < 2) return 1;
+            --depth;
+        } else {
+            return 1;
+        }
+        if (depth > OR_MAX_STACK) return 1;
+    }
+    return depth == 1 ? 0 : 1;
+}
+
+/* ---- 16-bit formats, from their definitions -------------------------------- */
+static float f32_from_bits(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+static uint32_t bits_from_f32(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+
+/* bfloat16 is the upper half of a binary32 pattern: widening is exact. */
+float oracle_bf16_to_f32(uint16_t h) { return f32_from_bits((uint32_t)h << 16); }
+
+/* Round a binary32 to bfloat16, nearest-even. The 16 dropped bits decide:
+ * above half rounds up, below half down, exactly half goes to the even
+ * neighbour. A carry out of the significand bumps the exponent, and the
+ * largest finite values round up to infinity, as IEEE rounding does. NaN stays
+ * NaN (quiet, sign kept). */
+uint16_t oracle_f32_to_bf16(float f) {
+    uint32_t u = bits_from_f32(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return (uint16_t)(((u >> 16) & 0x8000u) | 0x7fc0u);
+    uint32_t kept = u >> 16, dropped = u & 0xffffu;
+    if (dropped > 0x8000u || (dropped == 0x8000u && (kept & 1u))) ++kept;
+    return (uint16_t)kept;
+}
+
+/* binary16: 1 sign, 5 exponent (bias 15), 10 fraction bits. */
+float oracle_f16_to_f32(uint16_t h) {
+    uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+    uint32_t e = (h >> 10) & 0x1fu, m = h & 0x3ffu;
+    if (e == 0) {
+        /* zero or subnormal: m * 2^-24, exact in binary32 */
+        float v = ldexpf((float)m, -24);
+        return sign ? -v : v;
+    }
+    if (e == 31) return f32_from_bits(sign | 0x7f800000u | (m << 13));
+    return f32_from_bits(sign | ((e - 15u + 127u) << 23) | (m << 13));
+}
+
+/* Round a binary32 to binary16, nearest-even, with gradual underflow and
+ * overflow to infinity. */
+uint16_t oracle_f32_to_f16(float f) {
+    uint32_t u = bits_from_f32(f);
+    uint16_t sign = (uint16_t)((u >> 16) & 0x8000u);
+    int32_t e = (int32_t)((u >> 23) & 0xffu);
+    uint32_t m = u & 0x7fffffu;
+    if (e == 255) return (uint16_t)(sign | (m ? 0x7e00u : 0x7c00u));
+    int32_t E = e - 127 + 15; /* binary16 biased exponent of the value */
+    if (E >= 31) return (uint16_t)(sign | 0x7c00u);
+    if (E <= 0) {
+        /* result is subnormal (or rounds up to the smallest normal): value is
+         * sig * 2^(e-150), the binary16 subnormal step is 2^-24, so the
+         * result is sig / 2^(126-e) rounded to an integer. */
+        if (e == 0) return sign; /* binary32 subnormals are < 2^-126 */
+        uint32_t sig = m | 0x800000u;
+        int shift = 126 - e;
+        if (shift >= 32) return sign;
+        uint32_t q = sig >> shift, rem = sig & ((1u << shift) - 1u), half = 1u << (shift - 1);
+        if (rem > half || (rem == half && (q & 1u))) ++q;
+        return (uint16_t)(sign | q);
+    }
+    uint32_t q = ((uint32_t)E << 10) | (m >> 13), rem = m & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (q & 1u))) ++q; /* carry may reach inf: correct */
+    return (uint16_t)(sign | q);
+}
+
+/* Array forms of the conversions above (kind 0 = bfloat16, 1 = binary16). */
+void oracle_widen_h16(int kind, const uint16_t *h, double *out, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = (double)(kind == 0 ? oracle_bf16_to_f32(h[i]) : oracle_f16_to_f32(h[i]));
+}
+
+void oracle_narrow_h16(int kind, const float *f, uint16_t *out, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = kind == 0 ? oracle_f32_to_bf16(f[i]) : oracle_f32_to_f16(f[i]);
+}
+
+/* ---- element-wise evaluation: one stack machine run per element ----------- */
+
+int oracle_eval_f64(const uint32_t *prog, int len, const double *const *ops, int n_ops,
+                    const double *scalars, int n_sc, double *out, int64_t n) {
+    if (check_program(prog, len, n_ops, n_sc) || n < 0) return 1;
+    double st[OR_MAX_STACK];
+    for (int64_t i = 0; i < n; ++i) {
+        int sp = 0;
+        for (int t = 0; t < len; ++t) {
+            uint32_t op = prog[t] & 0xffu, arg = prog[t] >> 8;
+            if (op == OR_LOAD) { st[sp++] = ops[arg][i]; continue; }
+            if (op == OR_SCALAR) { st[sp++] = scalars[arg]; continue; }
+            double r = st[--sp], l = st[--sp];
+            st[sp++] = op == OR_ADD ? l + r : op == OR_SUB ? l - r : l * r;
+        }
+        out[i] = st[0];
+    }
+    return 0;
+}
+
+int oracle_eval_f32(const uint32_t *prog, int len, const float *const *ops, int n_ops,
+                    const double *scalars, int n_sc, float *out, int64_t n) {
+    if (check_program(prog, len, n_ops, n_sc) || n < 0) return 1;
+    float st[OR_MAX_STACK];
+    for (int64_t i = 0; i < n; ++i) {
+        int sp = 0;
+        for (int t = 0; t < len; ++t) {
+            uint32_t op = prog[t] & 0xffu, arg = prog[t] >> 8;
+            if (op == OR_LOAD) { st[sp++] = ops[arg][i]; continue; }
+            if (op == OR_SCALAR) { st[sp++] = (float)scalars[arg]; continue; }
+            float r = st[--sp], l = st[--sp];
+            st[sp++] = op == OR_ADD ? l + r : op == OR_SUB ? l - r : l * r;
+        }
+        out[i] = st[0];
+    }
+    return 0;
+}
+
+/* 16-bit storage: widen each loaded value, run the binary32 machine, narrow
+ * the result once. kind 0 = bfloat16, 1 = binary16. */
+int oracle_eval_h16(int kind, const uint32_t *prog, int len, const uint16_t *const *ops,
+                    int n_ops, const double *scalars, int n_sc, uint16_t *out, int64_t n) {
+    if (check_program(prog, len, n_ops, n_sc) || n < 0 || (kind != 0 && kind != 1)) return 1;
+    float st[OR_MAX_STACK];
+    for (int64_t i = 0; i < n; ++i) {
+        int sp = 0;
+        for (int t = 0; t < len; ++t) {
+            uint32_t op = prog[t] & 0xffu, arg = prog[t] >> 8;
+            if (op == OR_LOAD) {
+                uint16_t h = ops[arg][i];
+                st[sp++] = kind == 0 ? oracle_bf16_to_f32(h) : oracle_f16_to_f32(h);
+                continue;
+            }
+            if (op == OR_SCALAR) { st[sp++] = (float)scalars[arg]; continue; }
+            float r = st[--sp], l = st[--sp];
+            st[sp++] = op == OR_ADD ? l + r : op == OR_SUB ? l - r : l * r;
+        }
+        out[i] = kind == 0 ? oracle_f32_to_bf16(st[0]) : oracle_f32_to_f16(st[0]);
+    }
+    return 0;
+}
+
+/* ---- axpy: y <- alpha*x + y, alpha rounded once to the compute type ------- */
+
+int oracle_axpy_f64(int64_t n, double alpha, const double *x, double *y) {
+    if (n < 0) return 1;
+    for (int64_t i = 0; i < n; ++i) y[i] = alpha * x[i] + y[i];
+    return 0;
+}
+
+int oracle_axpy_f32(int64_t n, double alpha, const float *x, float *y) {
+    if (n < 0) return 1;
+    float a = (float)alpha;
+    for (int64_t i = 0; i < n; ++i) y[i] = a * x[i] + y[i];
+    return 0;
+}
+
+/* ---- reductions ------------------------------------------------------------ */
+
+/* Error-free transformations (Ogita-Rump-Oishi 2005, Sec. 3): a product split
+ * into its rounded value and exact error with one fused multiply-add, and a
+ * sum split into its rounded value and exact error (Knuth's TwoSum). */
+static void two_product(double a, double b, double *p, double *e) {
+    *p = a * b;
+    *e = fma(a, b, -*p);
+}
+static void two_sum(double a, double b, double *s, double *e) {
+    *s = a + b;
+    double z = *s - a;
+    *e = (a - (*s - z)) + (b - z);
+}
+
+/* Dot2: the running sum p is carried with its accumulated rounding errors s,
+ * which collect the exact error of every product and of every addition; the
+ * result is p + s. Also returns sum |x_i y_i| (the tolerance scale). */
+int oracle_dot2(int64_t n, const double *x, const double *y, double *result, double *abs_sum) {
+    if (n < 0) return 1;
+    double p = 0.0, s = 0.0, a = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double h, r, q;
+        two_product(x[i], y[i], &h, &r);
+        two_sum(p, h, &p, &q);
+        s = s + (q + r);
+        a = a + fabs(x[i] * y[i]);
+    }
+    *result = p + s;
+    if (abs_sum) *abs_sum = a;
+    return 0;
+}
+
+/* The unscaled 2-norm: square root of Dot2(x, x). */
+int oracle_nrm2(int64_t n, const double *x, double *result) {
+    double s;
+    if (oracle_dot2(n, x, x, &s, 0)) return 1;
+    *result = sqrt(s);
+    return 0;
+}
+
+/* Plain sequential loops: CPU timing baseline and same-precision FP32 mode. */
+double oracle_naive_dot_f64(int64_t n, const double *x, const double *y) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];
+    return s;
+}
+
+float oracle_naive_dot_f32(int64_t n, const float *x, const float *y) {
+    float s = 0.0f;
+    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];
+    return s;
+}

@@ -1,0 +1,70 @@
+"""Plant plausible mistakes in copies of the oracle (on the CPU) and check
+that the pins of ``test_oracle_pins.py`` catch every one of them.
+
+Each mutant is a one-line textual change of ``oracle/salt_oracle.c``, built
+with the oracle's own flags into a temporary directory. The real oracle is
+never modified.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+MUTANTS = {
+    # a transposed operand in SUB
+    "sub_swapped": ("op == OR_SUB ? l - r", "op == OR_SUB ? r - l"),
+    # the wrong scalar slot
+    "scalar_index": ("st[sp++] = (float)scalars[arg];", "st[sp++] = (float)scalars[0];"),
+    # the wrong operand slot in binary64
+    "load_index_f64": ("if (op == OR_LOAD) { st[sp++] = ops[arg][i]; continue; }\n            if (op == OR_SCALAR) { st[sp++] = scalars[arg]",
+                       "if (op == OR_LOAD) { st[sp++] = ops[0][i]; continue; }\n            if (op == OR_SCALAR) { st[sp++] = scalars[arg]"),
+    # a dropped term in Dot2 (the product's rounding error)
+    "dot2_drop_product_error": ("s = s + (q + r);", "s = s + q;"),
+    # a dropped term in TwoSum
+    "twosum_drop_term": ("*e = (a - (*s - z)) + (b - z);", "*e = (a - (*s - z));"),
+    # ties rounded up instead of to even (bfloat16)
+    "bf16_ties_up": ("if (dropped > 0x8000u || (dropped == 0x8000u && (kept & 1u))) ++kept;",
+                     "if (dropped >= 0x8000u) ++kept;"),
+    # truncation instead of rounding (binary16 normal range)
+    "f16_truncate": ("if (rem > 0x1000u || (rem == 0x1000u && (q & 1u))) ++q; /* carry",
+                     "if (0) ++q; /* carry"),
+    # an off-by-one exponent in binary16 gradual underflow
+    "f16_subnormal_shift": ("int shift = 126 - e;", "int shift = 125 - e;"),
+    # a wrong scale of binary16 subnormals on widening
+    "f16_widen_subnormal": ("ldexpf((float)m, -24)", "ldexpf((float)m, -25)"),
+    # nrm2 without its square root
+    "nrm2_no_sqrt": ("*result = sqrt(s);", "*result = s;"),
+    # axpy with its operands transposed
+    "axpy_transposed": ("y[i] = alpha * x[i] + y[i];", "y[i] = alpha * y[i] + x[i];"),
+    # binary32 scalars not rounded to binary32 before use (kept in binary64)
+    "f32_axpy_alpha_f64": ("for (int64_t i = 0; i < n; ++i) y[i] = a * x[i] + y[i];",
+                           "for (int64_t i = 0; i < n; ++i) y[i] = (float)(alpha * x[i] + y[i]);"),
+    # naive loop accumulating in the wrong precision
+    "naive_f32_in_f64": ("float s = 0.0f;\n    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];",
+                         "double s = 0.0;\n    for (int64_t i = 0; i < n; ++i) s = s + (double)x[i] * y[i];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path, monkeypatch):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "salt_oracle.c")).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) >= 1, "mutation site not found: %s" % name
+    mutated = src.replace(old, new)
+    c = tmp_path / "mutant.c"
+    c.write_text(mutated)
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", *oracle.CFLAGS, str(c), "-o", str(so), "-lm"])
+    monkeypatch.setattr(oracle, "_lib", oracle.load(str(so)))
+    failed = []
+    for check_name, check in pins.CHECKS.items():
+        try:
+            check(oracle)
+        except AssertionError:
+            failed.append(check_name)
+    assert failed, "no pin caught mutant %s" % name

@@ -1,0 +1,372 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each check is a function of the oracle module so that the mutation test
+(``test_oracle_mutants.py``) can run the same checks against deliberately
+broken builds of the oracle and see them fail.
+
+Pins used (none retypes the oracle's own loops):
+- the paper's Fig. 1 tree on hand-worked dyadic rows (``golden/``);
+- the same trees written as ordinary Python / numpy expressions (IEEE
+  binary64 / binary32 arithmetic of the interpreter and of numpy);
+- random postfix programs turned into infix source text and evaluated by
+  Python itself;
+- closed forms (a_i = i, b_i = 2i, c_i = i; dot = n(n-1)(2n-1)/3; nrm2 of
+  ones and of 0..n-1);
+- exact rational arithmetic (``fractions.Fraction``) and ``math.fsum`` for the
+  reductions, within the Dot2 error bound of Ogita, Rump and Oishi (2005);
+- torch / numpy conversions to bfloat16 / binary16 and hand-worked rounding
+  cases for the 16-bit storage formats.
+"""
+from __future__ import annotations
+
+import math
+import os
+import random
+import struct
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1109_1264_amd import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LOAD, SCALAR, ADD, SUB, MUL = 1, 2, 3, 4, 5
+U64 = 2.0 ** -53
+
+
+def tok(op, arg=0):
+    return (arg << 8) | op
+
+
+FIG1 = [tok(LOAD, 0), tok(LOAD, 1), tok(LOAD, 2), tok(SUB), tok(ADD)]          # a + (b - c)
+TREE5 = [tok(LOAD, 0), tok(LOAD, 1), tok(MUL), tok(LOAD, 2), tok(LOAD, 3), tok(MUL),
+         tok(ADD), tok(LOAD, 4), tok(SUB)]                                   # a*b + c*e - f
+AXPY = [tok(SCALAR, 0), tok(LOAD, 0), tok(MUL), tok(LOAD, 1), tok(ADD)]       # alpha*x + y
+
+
+def bits64(a):
+    return np.asarray(a, dtype=np.float64).view(np.uint64)
+
+
+def bits32(a):
+    return np.asarray(a, dtype=np.float32).view(np.uint32)
+
+
+def postfix_to_infix(prog):
+    """Source text of the expression a postfix program denotes
+    (pop r, pop l, push (l op r))."""
+    st = []
+    sym = {ADD: "+", SUB: "-", MUL: "*"}
+    for t in prog:
+        op, arg = t & 0xFF, t >> 8
+        if op == LOAD:
+            st.append("x%d" % arg)
+        elif op == SCALAR:
+            st.append("s%d" % arg)
+        else:
+            r = st.pop()
+            l = st.pop()
+            st.append("(%s %s %s)" % (l, sym[op], r))
+    assert len(st) == 1
+    return st[0]
+
+
+def random_program(rng, n_ops, n_sc, max_leaves=7):
+    """A random tree over the given operands and scalars, as postfix."""
+    def build(leaves):
+        if leaves == 1:
+            if n_sc and rng.random() < 0.25:
+                return [tok(SCALAR, rng.randrange(n_sc))]
+            return [tok(LOAD, rng.randrange(n_ops))]
+        k = rng.randrange(1, leaves)
+        return build(k) + build(leaves - k) + [tok(rng.choice([ADD, SUB, MUL]))]
+    return build(rng.randrange(1, max_leaves + 1))
+
+
+# --------------------------------------------------------------------------
+# element-wise: binary64
+# --------------------------------------------------------------------------
+
+def check_fig1_golden(o):
+    rows = [list(map(float, l.split())) for l in open(os.path.join(GOLDEN, "fig1_tree_dyadic.txt"))
+            if l.strip() and not l.startswith("#")]
+    a, b, c, d = (np.array(col) for col in zip(*rows))
+    for dt in ("f64", "f32"):
+        got = o.eval_program(FIG1, [a, b, c], [], dt)
+        assert np.array_equal(got, d.astype(got.dtype)), (dt, got, d)
+
+
+def check_python_float_trees_f64(o):
+    a, b, c, e, f = workloads.uniform(301, "f64", 11, 5)
+    got = o.eval_program(FIG1, [a, b, c], [], "f64")
+    want = [float(x) + (float(y) - float(z)) for x, y, z in zip(a, b, c)]
+    assert np.array_equal(bits64(got), bits64(want))
+    got = o.eval_program(TREE5, [a, b, c, e, f], [], "f64")
+    want = [float(p) * float(q) + float(r) * float(s) - float(t) for p, q, r, s, t in zip(a, b, c, e, f)]
+    assert np.array_equal(bits64(got), bits64(want))
+    al = workloads.alpha(11)
+    got = o.eval_program(AXPY, [a, b], [al], "f64")
+    want = [al * float(x) + float(y) for x, y in zip(a, b)]
+    assert np.array_equal(bits64(got), bits64(want))
+
+
+def check_random_programs(o, dtype, count=150):
+    rng = random.Random(1234 + len(dtype))
+    n = 67
+    np_t = np.float64 if dtype == "f64" else np.float32
+    for _ in range(count):
+        n_ops, n_sc = rng.randint(1, 8), rng.randint(0, 8)
+        prog = random_program(rng, n_ops, n_sc)
+        ops = workloads.uniform(n, dtype, rng.randrange(1 << 30), n_ops)
+        sc = [rng.uniform(-3, 3) for _ in range(n_sc)]
+        env = {"x%d" % k: ops[k] for k in range(n_ops)}
+        env.update({"s%d" % j: np_t(sc[j]) for j in range(n_sc)})
+        src = postfix_to_infix(prog)
+        want = np.broadcast_to(np.asarray(eval(src, {}, env), dtype=np_t), (n,))
+        got = o.eval_program(prog, ops, sc, dtype, n=n)
+        assert got.dtype == np_t
+        assert np.array_equal(got.view(np.uint64 if dtype == "f64" else np.uint32),
+                              np.ascontiguousarray(want).view(np.uint64 if dtype == "f64" else np.uint32)), src
+
+
+def check_closed_form(o):
+    n = 1 << 16
+    i = np.arange(n, dtype=np.float64)
+    got = o.eval_program(FIG1, [i, 2 * i, i], [], "f64")
+    assert np.array_equal(got, 2 * i)
+    m = 1 << 23  # 2i <= 2^24 stays exact in binary32
+    i32 = np.arange(0, m, 997, dtype=np.float32)
+    got = o.eval_program(FIG1, [i32, 2 * i32, i32], [], "f32")
+    assert np.array_equal(got, 2 * i32)
+
+
+def check_invariants(o, dtype):
+    a, b = workloads.uniform(513, dtype, 99, 2)
+    zero = o.eval_program([tok(LOAD, 0), tok(LOAD, 0), tok(SUB)], [a], [], dtype)
+    assert not np.any(zero.view(np.uint64 if dtype == "f64" else np.uint32))  # all +0
+    for op in (ADD, MUL):
+        ab = o.eval_program([tok(LOAD, 0), tok(LOAD, 1), tok(op)], [a, b], [], dtype)
+        ba = o.eval_program([tok(LOAD, 1), tok(LOAD, 0), tok(op)], [a, b], [], dtype)
+        assert np.array_equal(ab.view(np.uint8), ba.view(np.uint8))
+    one = o.eval_program([tok(LOAD, 0), tok(SCALAR, 0), tok(MUL)], [a], [1.0], dtype)
+    assert np.array_equal(one.view(np.uint8), a.view(np.uint8))
+    plus0 = o.eval_program([tok(LOAD, 0), tok(SCALAR, 0), tok(ADD)], [a], [0.0], dtype)
+    assert np.array_equal(plus0.view(np.uint8), a.view(np.uint8))
+
+
+def check_f32_numpy_trees(o):
+    a, b, c, e, f = workloads.uniform(1001, "f32", 5, 5)
+    assert np.array_equal(bits32(o.eval_program(FIG1, [a, b, c], [], "f32")), bits32(a + (b - c)))
+    assert np.array_equal(bits32(o.eval_program(TREE5, [a, b, c, e, f], [], "f32")),
+                          bits32(a * b + c * e - f))
+    # scalars are rounded once to binary32
+    al = 1.0 / 3.0
+    got = o.eval_program(AXPY, [a, b], [al], "f32")
+    assert np.array_equal(bits32(got), bits32(np.float32(al) * a + b))
+
+
+def check_subnormals(o):
+    # binary64 subnormals stay (no flush to zero)
+    tiny = np.array([5e-324, 2.5e-320, -1e-310, 2.2250738585072014e-308], dtype=np.float64)
+    got = o.eval_program([tok(LOAD, 0), tok(SCALAR, 0), tok(MUL)], [tiny], [0.5], "f64")
+    want = [float(t) * 0.5 for t in tiny]
+    assert np.array_equal(bits64(got), bits64(want))
+    t32 = np.array([1e-45, 3e-42, -1.1754942e-38, 1.17549435e-38], dtype=np.float32)
+    got = o.eval_program([tok(LOAD, 0), tok(LOAD, 0), tok(ADD)], [t32], [], "f32")
+    assert np.array_equal(bits32(got), bits32(t32 + t32))
+    assert np.all(got[:3] != 0)
+
+
+# --------------------------------------------------------------------------
+# 16-bit storage
+# --------------------------------------------------------------------------
+
+def check_rounding_golden(o):
+    for line in open(os.path.join(GOLDEN, "rounding_16bit.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        fmt, fbits, hbits = line.split()[:3]
+        f = struct.unpack("<f", struct.pack("<I", int(fbits, 16)))[0]
+        got = int(o.narrow([f], fmt)[0])
+        assert got == int(hbits, 16), (line, hex(got))
+
+
+def check_conversions_vs_libraries(o):
+    import torch
+
+    allh = np.arange(1 << 16, dtype=np.uint32).astype(np.uint16)
+    # widening: every 16-bit pattern (NaNs compared as NaN)
+    w_bf = o.widen(allh, "bf16")
+    ref_bf = torch.from_numpy(allh.view(np.int16)).view(torch.bfloat16).to(torch.float64).numpy()
+    w_h = o.widen(allh, "f16")
+    ref_h = allh.view(np.float16).astype(np.float64)
+    for got, ref in ((w_bf, ref_bf), (w_h, ref_h)):
+        nan = np.isnan(ref)
+        assert np.array_equal(np.isnan(got), nan)
+        assert np.array_equal(bits64(got[~nan]), bits64(ref[~nan]))
+    # narrowing: random binary32 patterns across all exponents, plus ties
+    rng = np.random.Generator(np.random.PCG64(77))
+    pats = rng.integers(0, 1 << 32, 400000, dtype=np.uint64).astype(np.uint32)
+    ties = (rng.integers(0, 1 << 16, 50000, dtype=np.uint64).astype(np.uint32) << 16) | 0x8000
+    ties16 = (rng.integers(0, 1 << 19, 50000, dtype=np.uint64).astype(np.uint32) << 13) | 0x1000
+    f = np.concatenate([pats, ties, ties16]).view(np.float32)
+    f = f[~np.isnan(f)]
+    got = o.narrow(f, "bf16")
+    ref = torch.from_numpy(f).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, ref)
+    got = o.narrow(f, "f16")
+    with np.errstate(over="ignore"):
+        ref = f.astype(np.float16).view(np.uint16)
+    assert np.array_equal(got, ref)
+
+
+def check_h16_eval_composition(o, dtype):
+    """16-bit storage eval = widen, binary32 ops, one narrowing (torch / numpy)."""
+    import torch
+
+    a, b, c, e, f = workloads.uniform(777, dtype, 21, 5)
+    tt = torch.bfloat16 if dtype == "bf16" else torch.float16
+
+    def wid(h):
+        return torch.from_numpy(h.view(np.int16)).view(tt).to(torch.float32).numpy()
+
+    def nar(x):
+        return torch.from_numpy(np.ascontiguousarray(x)).to(tt).view(torch.int16).numpy().view(np.uint16)
+
+    A, B, C, E, F = map(wid, (a, b, c, e, f))
+    assert np.array_equal(o.eval_program(FIG1, [a, b, c], [], dtype), nar(A + (B - C)))
+    assert np.array_equal(o.eval_program(TREE5, [a, b, c, e, f], [], dtype), nar(A * B + C * E - F))
+    al = 1.2345678901
+    assert np.array_equal(o.eval_program(AXPY, [a, b], [al], dtype), nar(np.float32(al) * A + B))
+
+
+# --------------------------------------------------------------------------
+# axpy
+# --------------------------------------------------------------------------
+
+def check_axpy(o):
+    x, y = workloads.uniform(999, "f64", 3, 2)
+    al = workloads.alpha(3)
+    got = o.axpy(al, x, y, "f64")
+    assert np.array_equal(bits64(got), bits64([al * float(p) + float(q) for p, q in zip(x, y)]))
+    x32, y32 = workloads.uniform(999, "f32", 3, 2)
+    got = o.axpy(al, x32, y32, "f32")
+    assert np.array_equal(bits32(got), bits32(np.float32(al) * x32 + y32))
+    # alpha = 2 on small integers is exact: y = 2x + y
+    i = np.arange(-500, 500, dtype=np.float64)
+    assert np.array_equal(o.axpy(2.0, i, 3 * i, "f64"), 5 * i)
+    assert np.array_equal(o.axpy(0.5, i.astype(np.float32), i.astype(np.float32), "f32"),
+                          (1.5 * i).astype(np.float32))
+
+
+# --------------------------------------------------------------------------
+# reductions
+# --------------------------------------------------------------------------
+
+def dot2_bound(n, exact_abs, sum_abs):
+    """Ogita-Rump-Oishi (2005) Prop. 5.5 bound for Dot2 in binary64."""
+    g = n * U64 / (1 - n * U64)
+    return U64 * exact_abs + g * g * sum_abs + 1e-300
+
+
+def check_dot_closed_form(o):
+    for n in (0, 1, 2, 3, 10, 1000, 1 << 17):
+        i = np.arange(n, dtype=np.float64)
+        r, _ = o.dot2(i, 2 * i)
+        assert r == n * (n - 1) * (2 * n - 1) // 3, n
+    # beyond 2^53 the value is no longer an integer in binary64: within Dot2's bound
+    n = 1 << 20
+    i = np.arange(n, dtype=np.float64)
+    r, s = o.dot2(i, 2 * i)
+    exact = Fraction(n * (n - 1) * (2 * n - 1), 3)
+    assert abs(Fraction(r) - exact) <= Fraction(dot2_bound(n, float(exact), s))
+
+
+def check_dot_fraction_bruteforce(o):
+    rng = np.random.Generator(np.random.PCG64(2024))
+    for trial in range(300):
+        n = int(rng.integers(0, 17))
+        x = rng.standard_normal(n) * 10.0 ** rng.integers(-5, 5, n)
+        y = rng.standard_normal(n) * 10.0 ** rng.integers(-5, 5, n)
+        if trial % 3 == 0 and n >= 2:   # cancellation: y ~ -x on half the terms
+            y[: n // 2] = -x[: n // 2] * (1 + 1e-12)
+        exact = sum((Fraction(float(p)) * Fraction(float(q)) for p, q in zip(x, y)), Fraction(0))
+        r, s = o.dot2(x, y)
+        assert abs(Fraction(r) - exact) <= Fraction(dot2_bound(n, abs(float(exact)), s)), (n, r, float(exact))
+
+
+def check_dot_fsum(o):
+    """binary32 inputs: every product is exact in binary64, so math.fsum of
+    the products is the correctly rounded exact dot product."""
+    x64, y64 = workloads.ill_conditioned(200000, 31)
+    x = x64.astype(np.float32).astype(np.float64)
+    y = y64.astype(np.float32).astype(np.float64)
+    exact = math.fsum((x * y).tolist())
+    r, s = o.dot2(x, y)
+    assert abs(r - exact) <= dot2_bound(len(x), abs(exact), s)
+    # and the plain binary64 loop is visibly worse than Dot2 on this data
+    assert abs(o.naive_dot(x, y) - exact) >= abs(r - exact)
+
+
+def check_nrm2(o):
+    for k in range(0, 11):
+        n = 4 ** k
+        assert o.nrm2(np.ones(n)) == 2.0 ** k
+    assert o.nrm2(np.zeros(0)) == 0.0
+    for n in (2, 7, 100, 4097):
+        i = np.arange(n, dtype=np.float64)
+        exact = Fraction((n - 1) * n * (2 * n - 1), 6)
+        r = o.nrm2(i)
+        # r is sqrt of a value within Dot2's bound, plus one rounding of sqrt
+        assert abs(r * r - float(exact)) <= 4 * U64 * float(exact), n
+    x = np.array([3.0, 4.0])
+    assert o.nrm2(x) == 5.0
+    assert o.nrm2(np.array([-2.0])) == 2.0
+
+
+def check_naive_f32(o):
+    x, y = workloads.uniform(300, "f32", 8, 2)
+    s = np.float32(0.0)
+    for p, q in zip(x, y):
+        s = np.float32(s + np.float32(p * q))
+    assert o.naive_dot(x, y, "f32") == float(s)
+
+
+# --------------------------------------------------------------------------
+# the tests
+# --------------------------------------------------------------------------
+
+CHECKS = {
+    "fig1_golden": check_fig1_golden,
+    "python_float_trees_f64": check_python_float_trees_f64,
+    "random_programs_f64": lambda o: check_random_programs(o, "f64"),
+    "random_programs_f32": lambda o: check_random_programs(o, "f32"),
+    "closed_form": check_closed_form,
+    "invariants_f64": lambda o: check_invariants(o, "f64"),
+    "invariants_f32": lambda o: check_invariants(o, "f32"),
+    "f32_numpy_trees": check_f32_numpy_trees,
+    "subnormals": check_subnormals,
+    "rounding_golden": check_rounding_golden,
+    "conversions_vs_libraries": check_conversions_vs_libraries,
+    "h16_eval_bf16": lambda o: check_h16_eval_composition(o, "bf16"),
+    "h16_eval_f16": lambda o: check_h16_eval_composition(o, "f16"),
+    "axpy": check_axpy,
+    "dot_closed_form": check_dot_closed_form,
+    "dot_fraction_bruteforce": check_dot_fraction_bruteforce,
+    "dot_fsum": check_dot_fsum,
+    "nrm2": check_nrm2,
+    "naive_f32": check_naive_f32,
+}
+
+
+@pytest.mark.parametrize("name", sorted(CHECKS))
+def test_oracle_pin(orc, name):
+    CHECKS[name](orc)
+
+
+def test_oracle_rejects_bad_programs(orc):
+    a = np.zeros(4)
+    for prog in ([tok(ADD)], [tok(LOAD, 0), tok(LOAD, 0)], [tok(LOAD, 3)], [tok(SCALAR, 0)], [9]):
+        with pytest.raises(ValueError):
+            orc.eval_program(prog, [a], [], "f64")
