@@ -1,0 +1,196 @@
+/*
+ * salt.h -- C ABI of libsalt: fused element-wise vector expressions, axpy,
+ * dot and nrm2 on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Progsch, Ineichen and Adelmann, "A New Vectorization Technique for
+ * Expression Templates in C++" (SALT). An expression over vectors is kept as
+ * a tree and evaluated lazily, in one loop over the elements, when it is
+ * assigned or reduced by a dot product or a norm (Sec. 2, Fig. 1); the loop
+ * issues a burst of loads, then the operations, then the stores (Sec. 4.3).
+ * Here the tree travels as a postfix program and the loop is a GPU kernel.
+ *
+ * Conventions shared by every entry point:
+ *  - Data pointers (operands, outputs, workspaces, results) are DEVICE
+ *    pointers owned by the caller; the library keeps none of them after the
+ *    call returns and allocates no device memory on these paths.
+ *  - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the default
+ *    stream) and the call returns without waiting. Outputs, including the
+ *    device scalar written by dot and nrm2, are valid once the stream has
+ *    reached that point.
+ *  - Vectors are contiguous, unit stride, one element type per call.
+ *    Lengths are int64; n == 0 is a no-op for eval/axpy and yields 0 for
+ *    dot/nrm2; n < 0 is SALT_ERR_ARG.
+ *  - Every argument or program error is reported before anything is
+ *    enqueued, with no partial effect. A failed launch returns
+ *    SALT_ERR_DEVICE. No C++ exception crosses this interface.
+ *    salt_last_error() gives a thread-local message for the last failure.
+ *  - Any element alignment is accepted; 16-byte aligned arrays take the
+ *    vectorised (16 B per lane) path, others a per-element path with the
+ *    same results (the paper's non-specialised fallback loop, Sec. 4.2).
+ */
+#ifndef SALT_H
+#define SALT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element (storage) types. F64 computes in binary64; F32, BF16 and F16
+ * compute in binary32 (16-bit values are widened exactly on load and rounded
+ * to nearest-even once on store). */
+typedef enum { SALT_F64 = 0, SALT_F32 = 1, SALT_BF16 = 2, SALT_F16 = 3 } salt_dtype;
+
+typedef enum {
+    SALT_OK = 0,
+    SALT_ERR_ARG = 1,         /* null pointer, bad length, bad dtype, overlap */
+    SALT_ERR_PROGRAM = 2,     /* malformed postfix program                     */
+    SALT_ERR_UNSUPPORTED = 3, /* valid request outside this build's limits     */
+    SALT_ERR_WORKSPACE = 4,   /* workspace missing, misaligned or too small    */
+    SALT_ERR_DEVICE = 5       /* HIP reported an error                         */
+} salt_status;
+
+/* Postfix program tokens: uint32 token = (arg << 8) | opcode.
+ * LOAD k    pushes operands[k][i]
+ * SCALAR j  pushes scalars[j], rounded once (nearest-even) to the compute type
+ * ADD/SUB/MUL pop r, pop l, push (l op r), rounded once, never contracted
+ *            into a fused multiply-add.
+ * A program is valid when every token is one of these, binary tokens have
+ * arg 0, k < n_operands, j < n_scalars, the stack never underflows, never
+ * holds more than SALT_MAX_STACK values, and ends with exactly one value.
+ * "Scale" is SCALAR j, <subtree>, MUL. */
+enum {
+    SALT_OP_LOAD = 1,
+    SALT_OP_SCALAR = 2,
+    SALT_OP_ADD = 3,
+    SALT_OP_SUB = 4,
+    SALT_OP_MUL = 5
+};
+#define SALT_TOKEN(op, arg) ((uint32_t)(((uint32_t)(arg) << 8) | (uint32_t)(op)))
+
+#define SALT_MAX_TOKENS 64
+#define SALT_MAX_OPERANDS 8
+#define SALT_MAX_SCALARS 8
+#define SALT_MAX_STACK 8
+
+/* Fused element-wise evaluation (Sec. 2, Fig. 1; loop structure Sec. 4.3):
+ *   out[i] = P(operands[0][i], ..., operands[n_operands-1][i]; scalars)
+ * for 0 <= i < n, in one pass over memory: inputs read once, out written
+ * once, intermediates kept in registers.
+ *  prog        host array of prog_len tokens (1..SALT_MAX_TOKENS)
+ *  operands    host array of n_operands device pointers (0..SALT_MAX_OPERANDS),
+ *              each to n elements of `dtype`
+ *  scalars     host array of n_scalars doubles (0..SALT_MAX_SCALARS)
+ *  out         device pointer to n elements of `dtype`; may be identical to an
+ *              operand pointer (in-place update) but must not partially
+ *              overlap any operand (SALT_ERR_ARG).
+ * Results are bit-identical to evaluating the postfix program element by
+ * element in the compute type, in program order. */
+salt_status salt_eval(const uint32_t *prog, int32_t prog_len,
+                      const void *const *operands, int32_t n_operands,
+                      const double *scalars, int32_t n_scalars,
+                      void *out, int64_t n, salt_dtype dtype, void *hip_stream);
+
+/* y <- alpha*x + y (Sec. 5, xAXPY): each element fl(fl(alpha*x) + y), alpha
+ * rounded once to the compute type, no fused multiply-add. x and y are
+ * device pointers to n elements; y is updated in place. */
+salt_status salt_axpy(int64_t n, double alpha, const void *x, void *y,
+                      salt_dtype dtype, void *hip_stream);
+
+/* Bytes of device workspace that salt_dot / salt_nrm2 need for length n
+ * (one binary64 partial per fixed-size tile of the input). 0 for n <= 0. */
+size_t salt_reduce_workspace_bytes(int64_t n, salt_dtype dtype);
+
+/* Dot product sum_i x[i]*y[i] (Sec. 2, reduction at the root of a tree;
+ * Sec. 4.2, the reduction step). The summation order depends only on n and
+ * dtype (fixed tiles, fixed in-tile order, fixed tree over tiles), so the
+ * result is bit-reproducible across calls, launch shapes and batching.
+ * Accumulation: binary64 for F64; for F32/BF16/F16 compensated binary32
+ * (error-free products and sums) per lane, binary64 across lanes and tiles.
+ *  result     device pointer to one double (F64) or one float (others)
+ *  workspace  device buffer, 8-byte aligned, >= salt_reduce_workspace_bytes */
+salt_status salt_dot(int64_t n, const void *x, const void *y, void *result,
+                     void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream);
+
+/* Euclidean norm sqrt(sum_i x[i]^2), unscaled (the paper's "norm", Sec. 2),
+ * with the same summation order, accumulation and arguments as salt_dot. */
+salt_status salt_nrm2(int64_t n, const void *x, void *result,
+                      void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream);
+
+/* ---- launch control (autotuning and introspection) ------------------------
+ * The paper picks the number of instruction packages per loop by trial
+ * (Sec. 4.3); here the equivalent knobs are chosen per tree, element type
+ * and size by a measured tuning table, and can be forced for measurement.
+ * None of them changes any result bit. */
+typedef struct {
+    int32_t unroll;      /* 16-byte chunks per operand per lane per burst:
+                          * eval 1, 2, 4, 8; dot/nrm2 2, 4, 8, 16; 0 = tuned */
+    int32_t nontemporal; /* 1 streaming loads/stores, 0 normal, -1 = tuned */
+    int64_t blocks;      /* workgroups: 0 = one per tile, >0 = grid-stride
+                          * grid of that size, -1 = tuned */
+} salt_launch_config;
+
+/* salt_eval with explicit launch knobs (cfg NULL = tuned). */
+salt_status salt_eval_ex(const uint32_t *prog, int32_t prog_len,
+                         const void *const *operands, int32_t n_operands,
+                         const double *scalars, int32_t n_scalars,
+                         void *out, int64_t n, salt_dtype dtype, void *hip_stream,
+                         const salt_launch_config *cfg);
+
+/* salt_dot / salt_nrm2 with explicit launch knobs (cfg NULL = tuned). */
+salt_status salt_dot_ex(int64_t n, const void *x, const void *y, void *result,
+                        void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream,
+                        const salt_launch_config *cfg);
+salt_status salt_nrm2_ex(int64_t n, const void *x, void *result,
+                         void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream,
+                         const salt_launch_config *cfg);
+
+/* Elements per reduction tile for dtype (the unit of the fixed order). */
+int64_t salt_reduce_tile_elems(salt_dtype dtype);
+
+/* Load a tuning table (text; one "kind route dtype log2n unroll nontemporal
+ * blocks" row per line, '#' comments; kind is eval, dot or nrm2; route is a
+ * catalogue index or -1 for the interpreter). NULL reloads the default file
+ * (SALT_TUNE_FILE, else salt_tuning.txt beside the library). Rows replace the
+ * current table. Returns SALT_ERR_ARG if the file cannot be read or parsed. */
+salt_status salt_tuning_load(const char *path);
+
+/* The knobs a call would use (kind 0 eval, 1 dot, 2 nrm2). */
+salt_status salt_tuning_lookup(int32_t kind, int32_t route, salt_dtype dtype, int64_t n,
+                               salt_launch_config *out);
+
+/* Trees compiled ahead of time. salt_catalogue_program copies tree i's
+ * canonical postfix form into tokens (up to cap) and returns its length, or
+ * -1 for a bad index; *name (if non-NULL) receives its name. */
+int32_t salt_catalogue_count(void);
+int32_t salt_catalogue_program(int32_t i, uint32_t *tokens, int32_t cap, const char **name);
+
+/* Which kernel a valid program runs on: *route = catalogue index, or -1 for
+ * the generic interpreter. Host only. */
+salt_status salt_program_route(const uint32_t *prog, int32_t prog_len,
+                               int32_t n_operands, int32_t n_scalars, int32_t *route);
+
+/* Validate a program without touching the GPU. On success fills
+ * *stack_need (maximum stack depth) and *n_loads (distinct operands read)
+ * when those pointers are non-null. */
+salt_status salt_program_check(const uint32_t *prog, int32_t prog_len,
+                               int32_t n_operands, int32_t n_scalars,
+                               int32_t *stack_need, int32_t *n_loads);
+
+/* Static description of a status code; never NULL. */
+const char *salt_status_string(salt_status s);
+
+/* Thread-local detail for the last non-OK status returned on this thread
+ * ("" if none). Valid until the next call on the same thread. */
+const char *salt_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t salt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SALT_H */

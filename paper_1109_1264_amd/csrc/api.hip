@@ -1,0 +1,409 @@
+// api.hip -- the C ABI (include/salt.h): argument checks, program routing,
+// launch-knob selection, and the launches themselves.
+//
+// This is the paper's execute function (Sec. 4.1, Fig. 2): it receives the
+// tree, picks the loop (an ahead-of-time kernel for a catalogue tree, else
+// the interpreter) and its unrolling (Sec. 4.3) and runs it. Every check
+// happens before the first HIP call, so a rejected call has no effect.
+#include <dlfcn.h>
+
+#include <cerrno>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "expr.hpp"
+#include "launch.hpp"
+#include "program.hpp"
+#include "salt.h"
+
+namespace salt {
+namespace {
+
+thread_local std::string t_err;
+
+salt_status fail(salt_status s, const std::string &m) {
+    t_err = m;
+    return s;
+}
+
+bool dtype_ok(int d) { return d >= SALT_F64 && d <= SALT_F16; }
+size_t esize(int d) { return d == SALT_F64 ? 8 : d == SALT_F32 ? 4 : 2; }
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+bool partial_overlap(const void *a, const void *b, size_t bytes) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    if (x == y) return false;
+    return x < y + bytes && y < x + bytes;
+}
+bool any_overlap(const void *a, size_t abytes, const void *b, size_t bbytes) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bbytes && y < x + abytes;
+}
+
+// ---- catalogue -------------------------------------------------------------
+struct CatEntry {
+    int len;
+    uint32_t tok[SALT_MAX_TOKENS];
+    const char *name;
+};
+
+const std::vector<CatEntry> &catalogue() {
+    static const std::vector<CatEntry> v = [] {
+        std::vector<CatEntry> r;
+        for (int id = 0; id < cat::count; ++id) {
+            CatEntry e;
+            e.name = "";
+            e.len = catalogue_program(id, e.tok, SALT_MAX_TOKENS, &e.name);
+            r.push_back(e);
+        }
+        return r;
+    }();
+    return v;
+}
+
+int route_of(const Program &p) {
+    const auto &c = catalogue();
+    for (size_t i = 0; i < c.size(); ++i)
+        if (c[i].len == p.len && std::memcmp(c[i].tok, p.canon, sizeof(uint32_t) * p.len) == 0)
+            return (int)i;
+    return kRouteGeneric;
+}
+
+// ---- tuning table ------------------------------------------------------------
+enum Kind { kEval = 0, kDot = 1, kNrm2 = 2 };
+
+struct TuneRow {
+    int kind, route, dtype, log2n;
+    salt_launch_config cfg;
+};
+
+std::mutex g_tune_mu;
+std::vector<TuneRow> g_tune;
+bool g_tune_loaded = false;
+
+std::string default_tune_path() {
+    if (const char *e = std::getenv("SALT_TUNE_FILE")) return e;
+    Dl_info info;
+    if (dladdr((void *)&salt_version, &info) && info.dli_fname) {
+        std::string f = info.dli_fname;
+        const size_t slash = f.rfind('/');
+        return (slash == std::string::npos ? std::string(".") : f.substr(0, slash)) + "/salt_tuning.txt";
+    }
+    return "salt_tuning.txt";
+}
+
+bool parse_tune(const std::string &path, std::vector<TuneRow> &rows, std::string *why) {
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) {
+        if (why) *why = "cannot open tuning file " + path;
+        return false;
+    }
+    char line[256];
+    int lineno = 0;
+    bool ok = true;
+    while (std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        char *h = std::strchr(line, '#');
+        if (h) *h = 0;
+        char kind[16];
+        int route, dtype, log2n, unroll, nt;
+        long long blocks;
+        int got = std::sscanf(line, "%15s %d %d %d %d %d %lld", kind, &route, &dtype, &log2n, &unroll, &nt, &blocks);
+        if (got <= 0) continue;
+        TuneRow r;
+        r.kind = !std::strcmp(kind, "eval") ? kEval : !std::strcmp(kind, "dot") ? kDot
+               : !std::strcmp(kind, "nrm2") ? kNrm2 : -1;
+        if (got != 7 || r.kind < 0 || !dtype_ok(dtype) || log2n < 0 || log2n > 62 || nt < 0 || nt > 1 || blocks < 0) {
+            if (why) *why = path + ": bad row at line " + std::to_string(lineno);
+            ok = false;
+            break;
+        }
+        r.route = route;
+        r.dtype = dtype;
+        r.log2n = log2n;
+        r.cfg.unroll = unroll;
+        r.cfg.nontemporal = nt;
+        r.cfg.blocks = blocks;
+        rows.push_back(r);
+    }
+    std::fclose(f);
+    return ok;
+}
+
+void ensure_tune_loaded() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    std::vector<TuneRow> rows;
+    if (parse_tune(default_tune_path(), rows, nullptr)) g_tune = rows;
+}
+
+int ilog2(int64_t n) {
+    int l = 0;
+    while (n > 1) n >>= 1, ++l;
+    return l;
+}
+
+// Defaults before any measurement: 4 chunks per operand per lane, streaming
+// hints above the 256 MiB last-level cache, one workgroup per tile.
+salt_launch_config default_cfg(int kind, int dtype, int64_t n, int n_arrays) {
+    salt_launch_config c;
+    const double bytes = (double)n * (double)esize(dtype) * n_arrays;
+    c.unroll = kind == kEval ? 4 : 8;
+    c.nontemporal = bytes >= 256.0 * 1024 * 1024 ? 1 : 0;
+    c.blocks = 0;
+    return c;
+}
+
+salt_launch_config lookup(int kind, int route, int dtype, int64_t n, int n_arrays) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    ensure_tune_loaded();
+    const int l = ilog2(n > 0 ? n : 1);
+    const TuneRow *best = nullptr;
+    int bestd = INT_MAX;
+    for (const auto &r : g_tune) {
+        if (r.kind != kind || r.route != route || r.dtype != dtype) continue;
+        const int d = std::abs(r.log2n - l);
+        if (d < bestd) bestd = d, best = &r;
+    }
+    return best ? best->cfg : default_cfg(kind, dtype, n, n_arrays);
+}
+
+salt_status resolve(const salt_launch_config *req, salt_launch_config tuned, bool eval,
+                    salt_launch_config *out) {
+    salt_launch_config c = tuned;
+    if (req) {
+        if (req->unroll != 0) c.unroll = req->unroll;
+        if (req->nontemporal >= 0) c.nontemporal = req->nontemporal;
+        if (req->blocks >= 0) c.blocks = req->blocks;
+        if (req->nontemporal > 1 || req->blocks < -1 || req->nontemporal < -1)
+            return fail(SALT_ERR_ARG, "launch config out of range");
+    }
+    const int u = c.unroll;
+    const bool ok = eval ? (u == 1 || u == 2 || u == 4 || u == 8) : (u == 2 || u == 4 || u == 8 || u == 16);
+    if (!ok) return fail(SALT_ERR_ARG, "unroll " + std::to_string(u) + " not available");
+    *out = c;
+    return SALT_OK;
+}
+
+salt_status device_status(hipError_t e) {
+    if (e == hipSuccess) return SALT_OK;
+    return fail(SALT_ERR_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+}
+
+salt_status eval_impl(const uint32_t *prog, int32_t prog_len, const void *const *operands,
+                      int32_t n_operands, const double *scalars, int32_t n_scalars, void *out,
+                      int64_t n, int dtype, void *stream, const salt_launch_config *cfg) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    if ((uint64_t)n > (uint64_t)INT64_MAX / 16) return fail(SALT_ERR_ARG, "length too large");
+    Program p;
+    std::string why;
+    salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, why);
+    if (p.n_loads > 0 && !operands) return fail(SALT_ERR_ARG, "operand array is NULL");
+    if (p.n_scal > 0 && !scalars) return fail(SALT_ERR_ARG, "scalar array is NULL");
+    const int route = route_of(p);
+    salt_launch_config c;
+    s = resolve(cfg, lookup(kEval, route, dtype, n, p.n_loads + 1), true, &c);
+    if (s != SALT_OK) return s;
+    if (n == 0) return SALT_OK;
+    if (!out) return fail(SALT_ERR_ARG, "output pointer is NULL");
+
+    EvalLaunch L;
+    std::memset(&L, 0, sizeof L);
+    const size_t bytes = (size_t)n * esize(dtype);
+    bool vec = aligned16(out);
+    for (int k = 0; k < p.n_loads; ++k) {
+        const void *a = operands[p.op_map[k]];
+        if (!a) return fail(SALT_ERR_ARG, "operand " + std::to_string(p.op_map[k]) + " is NULL");
+        if (partial_overlap(a, out, bytes))
+            return fail(SALT_ERR_ARG, "output partially overlaps operand " + std::to_string(p.op_map[k]));
+        L.ops[k] = a;
+        vec = vec && aligned16(a);
+    }
+    for (int j = 0; j < p.n_scal; ++j) L.sc[j] = scalars[p.sc_map[j]];
+    L.out = out;
+    L.n = n;
+    L.vec = vec ? 1 : 0;
+    L.unroll = c.unroll;
+    L.nontemporal = c.nontemporal;
+    L.blocks = c.blocks;
+    L.stream = stream;
+    if (route != kRouteGeneric) {
+        EvalFn fn = catalogue_launcher(route, dtype);
+        if (!fn) return fail(SALT_ERR_UNSUPPORTED, "no kernel for this tree and dtype");
+        return device_status(fn(L));
+    }
+    return device_status(launch_interp(L, p, dtype));
+}
+
+salt_status reduce_impl(int64_t n, const void *x, const void *y, void *result, void *ws,
+                        size_t ws_bytes, int dtype, void *stream, const salt_launch_config *cfg,
+                        bool nrm2) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    if ((uint64_t)n > (uint64_t)INT64_MAX / 16) return fail(SALT_ERR_ARG, "length too large");
+    if (!result) return fail(SALT_ERR_ARG, "result pointer is NULL");
+    if (n > 0 && (!x || (!nrm2 && !y))) return fail(SALT_ERR_ARG, "input pointer is NULL");
+    const size_t need = salt_reduce_workspace_bytes(n, (salt_dtype)dtype);
+    if (need > 0) {
+        if (!ws) return fail(SALT_ERR_WORKSPACE, "workspace is NULL");
+        if (((uintptr_t)ws & 7u) != 0) return fail(SALT_ERR_WORKSPACE, "workspace not 8-byte aligned");
+        if (ws_bytes < need)
+            return fail(SALT_ERR_WORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                                std::to_string(need));
+        const size_t bytes = (size_t)n * esize(dtype);
+        if (any_overlap(ws, need, x, bytes) || (!nrm2 && any_overlap(ws, need, y, bytes)))
+            return fail(SALT_ERR_WORKSPACE, "workspace overlaps an input");
+    }
+    salt_launch_config c;
+    salt_status s = resolve(cfg, lookup(nrm2 ? kNrm2 : kDot, -1, dtype, n, nrm2 ? 1 : 2), false, &c);
+    if (s != SALT_OK) return s;
+    ReduceLaunch L;
+    L.x = x;
+    L.y = nrm2 ? x : y;
+    L.result = result;
+    L.ws = (double *)ws;
+    L.n = n;
+    L.vec = aligned16(x) && (nrm2 || aligned16(y)) ? 1 : 0;
+    L.unroll = c.unroll;
+    L.nontemporal = c.nontemporal;
+    L.blocks = c.blocks;
+    L.nrm2 = nrm2 ? 1 : 0;
+    L.stream = stream;
+    return device_status(launch_reduce(L, dtype));
+}
+
+}  // namespace
+}  // namespace salt
+
+using namespace salt;
+
+extern "C" {
+
+salt_status salt_eval(const uint32_t *prog, int32_t prog_len, const void *const *operands,
+                      int32_t n_operands, const double *scalars, int32_t n_scalars, void *out,
+                      int64_t n, salt_dtype dtype, void *hip_stream) {
+    return eval_impl(prog, prog_len, operands, n_operands, scalars, n_scalars, out, n, dtype, hip_stream,
+                     nullptr);
+}
+
+salt_status salt_eval_ex(const uint32_t *prog, int32_t prog_len, const void *const *operands,
+                         int32_t n_operands, const double *scalars, int32_t n_scalars, void *out,
+                         int64_t n, salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
+    return eval_impl(prog, prog_len, operands, n_operands, scalars, n_scalars, out, n, dtype, hip_stream,
+                     cfg);
+}
+
+salt_status salt_axpy(int64_t n, double alpha, const void *x, void *y, salt_dtype dtype, void *hip_stream) {
+    static const uint32_t prog[5] = {SALT_TOKEN(SALT_OP_SCALAR, 0), SALT_TOKEN(SALT_OP_LOAD, 0),
+                                     SALT_TOKEN(SALT_OP_MUL, 0), SALT_TOKEN(SALT_OP_LOAD, 1),
+                                     SALT_TOKEN(SALT_OP_ADD, 0)};
+    if (n > 0 && dtype_ok(dtype) && x && y && x != y &&
+        any_overlap(x, (size_t)n * esize(dtype), y, (size_t)n * esize(dtype)))
+        return fail(SALT_ERR_ARG, "x partially overlaps y");
+    const void *ops[2] = {x, y};
+    return eval_impl(prog, 5, ops, 2, &alpha, 1, y, n, dtype, hip_stream, nullptr);
+}
+
+size_t salt_reduce_workspace_bytes(int64_t n, salt_dtype dtype) {
+    const int64_t T = reduce_tile_elems(dtype);
+    if (n <= 0 || T <= 0) return 0;
+    return (size_t)((n + T - 1) / T) * sizeof(double);
+}
+
+int64_t salt_reduce_tile_elems(salt_dtype dtype) { return reduce_tile_elems(dtype); }
+
+salt_status salt_dot(int64_t n, const void *x, const void *y, void *result, void *workspace,
+                     size_t ws_bytes, salt_dtype dtype, void *hip_stream) {
+    return reduce_impl(n, x, y, result, workspace, ws_bytes, dtype, hip_stream, nullptr, false);
+}
+
+salt_status salt_dot_ex(int64_t n, const void *x, const void *y, void *result, void *workspace,
+                        size_t ws_bytes, salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
+    return reduce_impl(n, x, y, result, workspace, ws_bytes, dtype, hip_stream, cfg, false);
+}
+
+salt_status salt_nrm2(int64_t n, const void *x, void *result, void *workspace, size_t ws_bytes,
+                      salt_dtype dtype, void *hip_stream) {
+    return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, nullptr, true);
+}
+
+salt_status salt_nrm2_ex(int64_t n, const void *x, void *result, void *workspace, size_t ws_bytes,
+                         salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
+    return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, cfg, true);
+}
+
+salt_status salt_tuning_load(const char *path) {
+    std::vector<TuneRow> rows;
+    std::string why;
+    const std::string p = path ? std::string(path) : default_tune_path();
+    if (!parse_tune(p, rows, &why)) return fail(SALT_ERR_ARG, why);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune = rows;
+    g_tune_loaded = true;
+    return SALT_OK;
+}
+
+salt_status salt_tuning_lookup(int32_t kind, int32_t route, salt_dtype dtype, int64_t n,
+                               salt_launch_config *out) {
+    if (!out || kind < 0 || kind > 2 || !dtype_ok(dtype)) return fail(SALT_ERR_ARG, "bad lookup arguments");
+    *out = lookup(kind, route, dtype, n, kind == kNrm2 ? 1 : 2);
+    return SALT_OK;
+}
+
+int32_t salt_catalogue_count(void) { return (int32_t)catalogue().size(); }
+
+int32_t salt_catalogue_program(int32_t i, uint32_t *tokens, int32_t cap, const char **name) {
+    const auto &c = catalogue();
+    if (i < 0 || i >= (int32_t)c.size()) return -1;
+    if (tokens)
+        for (int t = 0; t < c[i].len && t < cap; ++t) tokens[t] = c[i].tok[t];
+    if (name) *name = c[i].name;
+    return c[i].len;
+}
+
+salt_status salt_program_route(const uint32_t *prog, int32_t prog_len, int32_t n_operands,
+                               int32_t n_scalars, int32_t *route) {
+    Program p;
+    std::string why;
+    const salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, why);
+    if (route) *route = route_of(p);
+    return SALT_OK;
+}
+
+salt_status salt_program_check(const uint32_t *prog, int32_t prog_len, int32_t n_operands,
+                               int32_t n_scalars, int32_t *stack_need, int32_t *n_loads) {
+    Program p;
+    std::string why;
+    const salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, why);
+    if (stack_need) *stack_need = p.stack_need;
+    if (n_loads) *n_loads = p.n_loads;
+    return SALT_OK;
+}
+
+const char *salt_status_string(salt_status s) {
+    switch (s) {
+        case SALT_OK: return "ok";
+        case SALT_ERR_ARG: return "invalid argument";
+        case SALT_ERR_PROGRAM: return "invalid program";
+        case SALT_ERR_UNSUPPORTED: return "unsupported";
+        case SALT_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        case SALT_ERR_DEVICE: return "device error";
+        default: return "unknown status";
+    }
+}
+
+const char *salt_last_error(void) { return t_err.c_str(); }
+
+int32_t salt_version(void) { return 10000; }
+
+}  // extern "C"

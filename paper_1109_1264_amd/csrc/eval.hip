@@ -1,0 +1,309 @@
+// eval.hip -- fused element-wise evaluation kernels for gfx950.
+//
+// One kernel pass evaluates a whole expression tree per element (loop
+// fusion, Sec. 2): every operand is read once, the result written once, and
+// intermediates stay in registers. The loop body follows the paper's
+// instruction packages (Sec. 4.3): each lane first issues all of its 16-byte
+// loads for a tile (U chunks per operand), then evaluates the tree on the
+// loaded registers, then issues all of its stores. U plays the role of the
+// paper's number of packages per loop, picked by measurement per tree, type
+// and size (Sec. 4.3, last paragraph), and the 16-byte chunk the role of its
+// SIMD vector. Elements after the last whole tile, and every element when an
+// array is not 16-byte aligned, go through a per-element loop: the paper's
+// scalar tail (Listing 2) and its non-specialised fallback.
+//
+// Two kernel families:
+//  * k_eval_tree<E, ...>: the tree E is a compile-time type (expr.hpp) and the
+//    kernel is straight-line code for it (ahead-of-time catalogue).
+//  * k_eval_interp<...>: any valid program. The program is uniform across the
+//    grid, so its instruction loop runs on the scalar unit; each instruction
+//    code names its stack slot, so the per-lane stack is a register array
+//    indexed by constants inside each case of the switch.
+#include "device.hpp"
+#include "expr.hpp"
+#include "launch.hpp"
+
+namespace salt {
+
+template <int DT>
+struct EvalArgs {
+    const void *ops[SALT_MAX_OPERANDS];
+    typename Tr<DT>::C sc[SALT_MAX_SCALARS];
+    void *out;
+    int64_t n;
+    int32_t vec;  // 1: 16-byte path for whole tiles; 0: per-element path only
+};
+
+// Operand values of one lane's tile: element p of chunk u of operand K.
+template <int DT, int NL, int U, int NS>
+struct ChunkCtx {
+    using C = typename Tr<DT>::C;
+    const u32x4 (&raw)[NL][U];
+    const C (&s)[NS];
+    int u, p;
+    template <int K>
+    __device__ __forceinline__ C ld() const { return Tr<DT>::get(raw[K][u], p); }
+    template <int J>
+    __device__ __forceinline__ C sc() const { return s[J]; }
+};
+
+// Operand values of one element, loaded one by one.
+template <int DT, int NL, int NS>
+struct ElemCtx {
+    using C = typename Tr<DT>::C;
+    const void *const (&op)[NL];
+    const C (&s)[NS];
+    int64_t i;
+    template <int K>
+    __device__ __forceinline__ C ld() const { return Tr<DT>::ld1(op[K], i); }
+    template <int J>
+    __device__ __forceinline__ C sc() const { return s[J]; }
+};
+
+template <class E, int DT, int U, bool NT>
+__global__ __launch_bounds__(kBlock) void k_eval_tree(EvalArgs<DT> a) {
+    using C = typename Tr<DT>::C;
+    constexpr int V = Tr<DT>::V;
+    constexpr int NL = E::n_loads > 0 ? E::n_loads : 1;
+    constexpr int NS = E::n_scal > 0 ? E::n_scal : 1;
+    const void *op[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) op[k] = a.ops[k];
+    C s[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) s[j] = a.sc[j];
+
+    constexpr int64_t tile = (int64_t)kBlock * U * V;
+    const int64_t n_tiles = a.vec ? a.n / tile : 0;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int64_t c0 = t * (kBlock * U) + threadIdx.x;  // this lane's first chunk
+        u32x4 raw[NL][U];
+#pragma unroll
+        for (int k = 0; k < E::n_loads; ++k)
+#pragma unroll
+            for (int u = 0; u < U; ++u) raw[k][u] = ld16<NT>((const u32x4 *)op[k] + c0 + u * kBlock);
+        u32x4 res[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            C r[V];
+#pragma unroll
+            for (int p = 0; p < V; ++p) r[p] = E::ev(ChunkCtx<DT, NL, U, NS>{raw, s, u, p});
+            res[u] = Tr<DT>::template pack<V>(r);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) st16<NT>((u32x4 *)a.out + c0 + u * kBlock, res[u]);
+    }
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = n_tiles * tile + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += stride)
+        Tr<DT>::st1(a.out, i, E::ev(ElemCtx<DT, NL, NS>{op, s, i}));
+}
+
+// ---------------------------------------------------------------------------
+// generic interpreter
+// ---------------------------------------------------------------------------
+
+struct InterpProg {
+    uint8_t code[SALT_MAX_TOKENS];
+    uint8_t sarg[SALT_MAX_TOKENS];
+    int32_t len;
+    int32_t n_loads;
+};
+
+#define SALT_S8(M, k) M(k, 0) M(k, 1) M(k, 2) M(k, 3) M(k, 4) M(k, 5) M(k, 6) M(k, 7)
+#define SALT_K8(M) SALT_S8(M, 0) SALT_S8(M, 1) SALT_S8(M, 2) SALT_S8(M, 3) \
+    SALT_S8(M, 4) SALT_S8(M, 5) SALT_S8(M, 6) SALT_S8(M, 7)
+#define SALT_SLOTS7(M, op) M(op, 0) M(op, 1) M(op, 2) M(op, 3) M(op, 4) M(op, 5) M(op, 6)
+
+// Run program `g` for EL elements per lane; get(k, j) yields element j of
+// operand k. The result ends in st[0].
+template <int EL, class C, class Get>
+__device__ __forceinline__ void interp_run(const InterpProg &g, const C *sc, const Get &get,
+                                           C (&st)[SALT_MAX_STACK][EL]) {
+    for (int t = 0; t < g.len; ++t) {
+        // The program is the same for every lane: say so, so that the switch
+        // is a scalar branch rather than a divergent one.
+        switch (__builtin_amdgcn_readfirstlane(g.code[t])) {
+#define SALT_LOAD_CASE(k, s)                                   \
+    case (k) * 8 + (s): {                                      \
+        _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = get(k, j); \
+    } break;
+            SALT_K8(SALT_LOAD_CASE)
+#undef SALT_LOAD_CASE
+#define SALT_SCALAR_CASE(z, s)                                 \
+    case 64 + (s): {                                           \
+        const C v = sc[__builtin_amdgcn_readfirstlane(g.sarg[t])]; \
+        _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = v; \
+    } break;
+            SALT_S8(SALT_SCALAR_CASE, 0)
+#undef SALT_SCALAR_CASE
+#define SALT_ADD_CASE(z, s) \
+    case 72 + (s): { _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = st[s][j] + st[s + 1][j]; } break;
+#define SALT_SUB_CASE(z, s) \
+    case 80 + (s): { _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = st[s][j] - st[s + 1][j]; } break;
+#define SALT_MUL_CASE(z, s) \
+    case 88 + (s): { _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = st[s][j] * st[s + 1][j]; } break;
+            SALT_SLOTS7(SALT_ADD_CASE, 0)
+            SALT_SLOTS7(SALT_SUB_CASE, 0)
+            SALT_SLOTS7(SALT_MUL_CASE, 0)
+#undef SALT_ADD_CASE
+#undef SALT_SUB_CASE
+#undef SALT_MUL_CASE
+            default:
+                break;
+        }
+    }
+}
+
+template <int DT, int U, bool NT>
+__global__ __launch_bounds__(kBlock) void k_eval_interp(EvalArgs<DT> a, InterpProg g) {
+    using C = typename Tr<DT>::C;
+    constexpr int V = Tr<DT>::V;
+    constexpr int64_t tile = (int64_t)kBlock * U * V;
+    const int64_t n_tiles = a.vec ? a.n / tile : 0;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int64_t c0 = t * (kBlock * U) + threadIdx.x;
+        u32x4 raw[SALT_MAX_OPERANDS][U];
+#pragma unroll
+        for (int k = 0; k < SALT_MAX_OPERANDS; ++k)
+            if (k < g.n_loads)
+#pragma unroll
+                for (int u = 0; u < U; ++u) raw[k][u] = ld16<NT>((const u32x4 *)a.ops[k] + c0 + u * kBlock);
+        C st[SALT_MAX_STACK][U * V];
+        interp_run<U * V>(g, a.sc, [&](int k, int j) { return Tr<DT>::get(raw[k][j / V], j % V); }, st);
+#pragma unroll
+        for (int u = 0; u < U; ++u) st16<NT>((u32x4 *)a.out + c0 + u * kBlock, Tr<DT>::template pack<V>(&st[0][u * V]));
+    }
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = n_tiles * tile + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += stride) {
+        C st[SALT_MAX_STACK][1];
+        interp_run<1>(g, a.sc, [&](int k, int) { return Tr<DT>::ld1(a.ops[k], i); }, st);
+        Tr<DT>::st1(a.out, i, st[0][0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+template <int DT>
+static EvalArgs<DT> make_args(const EvalLaunch &L) {
+    EvalArgs<DT> a;
+    for (int k = 0; k < SALT_MAX_OPERANDS; ++k) a.ops[k] = L.ops[k];
+    // Scalars are rounded once (nearest-even) to the compute type here.
+    for (int j = 0; j < SALT_MAX_SCALARS; ++j) a.sc[j] = (typename Tr<DT>::C)L.sc[j];
+    a.out = L.out;
+    a.n = L.n;
+    a.vec = L.vec;
+    return a;
+}
+
+template <int DT>
+static dim3 grid_for(const EvalLaunch &L, int U) {
+    const int64_t tile = (int64_t)kBlock * U * Tr<DT>::V;
+    const int64_t n_tiles = L.vec ? L.n / tile : 0;
+    int64_t g;
+    if (n_tiles > 0) {
+        g = L.blocks > 0 ? (L.blocks < n_tiles ? L.blocks : n_tiles) : n_tiles;
+    } else {
+        g = (L.n + kBlock - 1) / kBlock;
+        const int64_t cap = L.blocks > 0 ? L.blocks : 8192;
+        if (g > cap) g = cap;
+    }
+    if (g < 1) g = 1;
+    if (g > 0x7fffffff) g = 0x7fffffff;
+    return dim3((unsigned)g);
+}
+
+template <class E, int DT, int U, bool NT>
+static hipError_t launch_tree_u(const EvalLaunch &L) {
+    hipLaunchKernelGGL((k_eval_tree<E, DT, U, NT>), grid_for<DT>(L, U), dim3(kBlock), 0,
+                       (hipStream_t)L.stream, make_args<DT>(L));
+    return hipGetLastError();
+}
+
+template <class E, int DT>
+static hipError_t launch_tree(const EvalLaunch &L) {
+    const bool nt = L.nontemporal != 0;
+    switch (L.unroll) {
+        case 1: return nt ? launch_tree_u<E, DT, 1, true>(L) : launch_tree_u<E, DT, 1, false>(L);
+        case 2: return nt ? launch_tree_u<E, DT, 2, true>(L) : launch_tree_u<E, DT, 2, false>(L);
+        case 4: return nt ? launch_tree_u<E, DT, 4, true>(L) : launch_tree_u<E, DT, 4, false>(L);
+        case 8: return nt ? launch_tree_u<E, DT, 8, true>(L) : launch_tree_u<E, DT, 8, false>(L);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class E>
+static EvalFn tree_fn(int dtype) {
+    switch (dtype) {
+        case SALT_F64: return &launch_tree<E, SALT_F64>;
+        case SALT_F32: return &launch_tree<E, SALT_F32>;
+        case SALT_BF16: return &launch_tree<E, SALT_BF16>;
+        case SALT_F16: return &launch_tree<E, SALT_F16>;
+        default: return nullptr;
+    }
+}
+
+EvalFn catalogue_launcher(int id, int dtype) {
+    switch (id) {
+#define SALT_CAT_CASE(name, ...) \
+    case cat::id_##name: return tree_fn<cat::name>(dtype);
+        SALT_CATALOGUE(SALT_CAT_CASE)
+#undef SALT_CAT_CASE
+        default: return nullptr;
+    }
+}
+
+int catalogue_program(int id, uint32_t *tokens, int cap, const char **name) {
+    uint32_t buf[SALT_MAX_TOKENS];
+    int len = 0;
+    switch (id) {
+#define SALT_CAT_EMIT(nm, ...)       \
+    case cat::id_##nm:               \
+        cat::nm::emit(buf, len);     \
+        if (name) *name = #nm;       \
+        break;
+        SALT_CATALOGUE(SALT_CAT_EMIT)
+#undef SALT_CAT_EMIT
+        default: return -1;
+    }
+    for (int t = 0; t < len && t < cap; ++t) tokens[t] = buf[t];
+    return len;
+}
+
+template <int DT, int U, bool NT>
+static hipError_t launch_interp_u(const EvalLaunch &L, const InterpProg &g) {
+    hipLaunchKernelGGL((k_eval_interp<DT, U, NT>), grid_for<DT>(L, U), dim3(kBlock), 0,
+                       (hipStream_t)L.stream, make_args<DT>(L), g);
+    return hipGetLastError();
+}
+
+// The interpreter keeps 8 stack slots of U*V values per lane in registers.
+// U is fixed per type: 2 chunks for binary64 and binary32, 1 chunk for 16-bit
+// storage, the shapes that compile without register spills (one chunk of
+// binary64 or binary32 per slot makes the compiler spill).
+template <int DT>
+static hipError_t launch_interp_dt(const EvalLaunch &L, const InterpProg &g) {
+    constexpr int U = Tr<DT>::V >= 8 ? 1 : 2;
+    const bool nt = L.nontemporal != 0;
+    return nt ? launch_interp_u<DT, U, true>(L, g) : launch_interp_u<DT, U, false>(L, g);
+}
+
+hipError_t launch_interp(const EvalLaunch &L, const Program &p, int dtype) {
+    InterpProg g;
+    for (int t = 0; t < SALT_MAX_TOKENS; ++t) {
+        g.code[t] = t < p.len ? p.code[t] : 0;
+        g.sarg[t] = t < p.len ? p.sarg[t] : 0;
+    }
+    g.len = p.len;
+    g.n_loads = p.n_loads;
+    switch (dtype) {
+        case SALT_F64: return launch_interp_dt<SALT_F64>(L, g);
+        case SALT_F32: return launch_interp_dt<SALT_F32>(L, g);
+        case SALT_BF16: return launch_interp_dt<SALT_BF16>(L, g);
+        case SALT_F16: return launch_interp_dt<SALT_F16>(L, g);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace salt

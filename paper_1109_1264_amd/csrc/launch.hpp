@@ -1,0 +1,54 @@
+// launch.hpp -- host-side interface between the C ABI and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "program.hpp"
+#include "salt.h"
+
+namespace salt {
+
+// One element-wise launch: canonical operand pointers and scalars, shape and
+// tuning knobs.
+struct EvalLaunch {
+    const void *ops[SALT_MAX_OPERANDS];
+    double sc[SALT_MAX_SCALARS];
+    void *out;
+    int64_t n;
+    int32_t vec;          // all arrays 16-byte aligned
+    int32_t unroll;       // 16-byte chunks per operand per lane per tile
+    int32_t nontemporal;  // streaming loads/stores
+    int64_t blocks;       // 0 = one workgroup per tile, else grid size
+    void *stream;
+};
+
+using EvalFn = hipError_t (*)(const EvalLaunch &);
+
+// Ahead-of-time kernel launcher for catalogue tree `id` and `dtype`, or null.
+EvalFn catalogue_launcher(int id, int dtype);
+// Postfix form of catalogue tree `id` (canonical numbering) and its name;
+// returns its length, or -1 for an unknown id.
+int catalogue_program(int id, uint32_t *tokens, int cap, const char **name);
+// Generic interpreter launch for a compiled program.
+hipError_t launch_interp(const EvalLaunch &L, const Program &p, int dtype);
+
+// Reductions (reduce.hip).
+struct ReduceLaunch {
+    const void *x;
+    const void *y;  // == x for nrm2
+    void *result;
+    double *ws;     // one binary64 partial per tile
+    int64_t n;
+    int32_t vec;
+    int32_t unroll;     // chunks per lane per load burst
+    int32_t nontemporal;
+    int64_t blocks;     // 0 = one workgroup per tile, else grid size
+    int32_t nrm2;
+    void *stream;
+};
+int64_t reduce_tile_elems(int dtype);
+hipError_t launch_reduce(const ReduceLaunch &L, int dtype);
+
+}  // namespace salt

@@ -1,0 +1,285 @@
+"""Thin ctypes binding of ``libsalt.so`` (include/salt.h), same names.
+
+Only argument marshalling happens here: torch tensors are turned into device
+pointers and the current HIP stream, and every computation runs in the
+library's kernels. There is no fallback: if the library is missing the first
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsalt.so")
+
+# Element types and status codes (include/salt.h).
+F64, F32, BF16, F16 = 0, 1, 2, 3
+OK, ERR_ARG, ERR_PROGRAM, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = range(6)
+LOAD, SCALAR, ADD, SUB, MUL = 1, 2, 3, 4, 5
+MAX_TOKENS, MAX_OPERANDS, MAX_SCALARS, MAX_STACK = 64, 8, 8, 8
+
+DTYPE_NAMES = {F64: "f64", F32: "f32", BF16: "bf16", F16: "f16"}
+ELEM_BYTES = {F64: 8, F32: 4, BF16: 2, F16: 2}
+
+
+def token(op: int, arg: int = 0) -> int:
+    return ((arg << 8) | op) & 0xFFFFFFFF
+
+
+class SaltError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("salt status %d (%s): %s" % (status, _status_string(status), message))
+        self.status = status
+
+
+class LaunchConfig(ctypes.Structure):
+    """salt_launch_config: unroll (0 = tuned), nontemporal (-1 = tuned),
+    blocks (-1 = tuned, 0 = one workgroup per tile)."""
+    _fields_ = [("unroll", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("blocks", ctypes.c_int64)]
+
+    def __init__(self, unroll=0, nontemporal=-1, blocks=-1):
+        super().__init__(unroll, nontemporal, blocks)
+
+    def as_tuple(self):
+        return (self.unroll, self.nontemporal, self.blocks)
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsalt.so and declare its C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsalt.so is not built (run python -m paper_1109_1264_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    U32P = ctypes.POINTER(ctypes.c_uint32)
+    CFG = ctypes.POINTER(LaunchConfig)
+    sigs = {
+        "salt_eval": ([U32P, I32, P, I32, P, I32, P, I64, I32, P], I32),
+        "salt_eval_ex": ([U32P, I32, P, I32, P, I32, P, I64, I32, P, CFG], I32),
+        "salt_axpy": ([I64, D, P, P, I32, P], I32),
+        "salt_reduce_workspace_bytes": ([I64, I32], SZ),
+        "salt_reduce_tile_elems": ([I32], I64),
+        "salt_dot": ([I64, P, P, P, P, SZ, I32, P], I32),
+        "salt_dot_ex": ([I64, P, P, P, P, SZ, I32, P, CFG], I32),
+        "salt_nrm2": ([I64, P, P, P, SZ, I32, P], I32),
+        "salt_nrm2_ex": ([I64, P, P, P, SZ, I32, P, CFG], I32),
+        "salt_tuning_load": ([ctypes.c_char_p], I32),
+        "salt_tuning_lookup": ([I32, I32, I32, I64, CFG], I32),
+        "salt_catalogue_count": ([], I32),
+        "salt_catalogue_program": ([I32, U32P, I32, ctypes.POINTER(ctypes.c_char_p)], I32),
+        "salt_program_route": ([U32P, I32, I32, I32, ctypes.POINTER(I32)], I32),
+        "salt_program_check": ([U32P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)], I32),
+        "salt_status_string": ([I32], ctypes.c_char_p),
+        "salt_last_error": ([], ctypes.c_char_p),
+        "salt_version": ([], I32),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _status_string(s: int) -> str:
+    try:
+        return lib().salt_status_string(s).decode()
+    except Exception:  # pragma: no cover - only used in error text
+        return "?"
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise SaltError(status, lib().salt_last_error().decode())
+
+
+def _prog(tokens: Sequence[int]):
+    arr = (ctypes.c_uint32 * max(1, len(tokens)))(*[int(t) & 0xFFFFFFFF for t in tokens])
+    return arr, len(tokens)
+
+
+# ---------------------------------------------------------------------------
+# torch plumbing (device memory and streams only)
+# ---------------------------------------------------------------------------
+
+def dtype_code(t) -> int:
+    import torch
+
+    m = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+    if t.dtype not in m:
+        raise TypeError("unsupported tensor dtype %s" % t.dtype)
+    return m[t.dtype]
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev(t):
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if t.dim() != 1 or (t.numel() > 1 and t.stride(0) != 1):
+        raise ValueError("tensors must be contiguous 1-D vectors")
+    return t.data_ptr()
+
+
+def _cfg(config):
+    if config is None:
+        return None
+    if isinstance(config, LaunchConfig):
+        return ctypes.byref(config)
+    return ctypes.byref(LaunchConfig(*config))
+
+
+def salt_eval(prog: Sequence[int], operands, scalars, out, n: int | None = None,
+              stream=None, config=None) -> None:
+    """out[i] = prog(operands[...][i]; scalars) on the GPU (see salt.h)."""
+    d = dtype_code(out)
+    for t in operands:
+        if dtype_code(t) != d:
+            raise TypeError("all operands must have the output's dtype")
+    if n is None:
+        n = out.numel()
+    for t in list(operands) + [out]:
+        if t.numel() < n:
+            raise ValueError("tensor shorter than n")
+    parr, plen = _prog(prog)
+    ops = (ctypes.c_void_p * max(1, len(operands)))(*[_dev(t) for t in operands])
+    sc = (ctypes.c_double * max(1, len(scalars)))(*[float(s) for s in scalars])
+    L = lib()
+    if config is None:
+        st = L.salt_eval(parr, plen, ops, len(operands), sc, len(scalars), _dev(out), n, d, _stream_ptr(stream))
+    else:
+        st = L.salt_eval_ex(parr, plen, ops, len(operands), sc, len(scalars), _dev(out), n, d,
+                            _stream_ptr(stream), _cfg(config))
+    check(st)
+
+
+def salt_axpy(alpha: float, x, y, n: int | None = None, stream=None) -> None:
+    """y <- alpha*x + y."""
+    d = dtype_code(y)
+    if dtype_code(x) != d:
+        raise TypeError("x and y must share a dtype")
+    if n is None:
+        n = y.numel()
+    if x.numel() < n or y.numel() < n:
+        raise ValueError("tensor shorter than n")
+    check(lib().salt_axpy(n, float(alpha), _dev(x), _dev(y), d, _stream_ptr(stream)))
+
+
+def salt_reduce_workspace_bytes(n: int, dtype: int) -> int:
+    return int(lib().salt_reduce_workspace_bytes(n, dtype))
+
+
+def salt_reduce_tile_elems(dtype: int) -> int:
+    return int(lib().salt_reduce_tile_elems(dtype))
+
+
+def workspace(n: int, dtype: int, device="cuda"):
+    """A device workspace of the size dot / nrm2 need for length n."""
+    import torch
+
+    nbytes = salt_reduce_workspace_bytes(n, dtype)
+    return torch.empty(max(1, (nbytes + 7) // 8), dtype=torch.float64, device=device)
+
+
+def _result_tensor(d, device):
+    import torch
+
+    return torch.empty(1, dtype=torch.float64 if d == F64 else torch.float32, device=device)
+
+
+def salt_dot(x, y, n: int | None = None, result=None, ws=None, stream=None, config=None):
+    """Device scalar sum x[i]*y[i] (binary64 for F64, else binary32)."""
+    d = dtype_code(x)
+    if dtype_code(y) != d:
+        raise TypeError("x and y must share a dtype")
+    if n is None:
+        n = x.numel()
+    if x.numel() < n or y.numel() < n:
+        raise ValueError("tensor shorter than n")
+    result = _result_tensor(d, x.device) if result is None else result
+    ws = workspace(n, d, x.device) if ws is None else ws
+    nb = ws.numel() * ws.element_size()
+    L = lib()
+    if config is None:
+        st = L.salt_dot(n, _dev(x), _dev(y), _dev(result), _dev(ws), nb, d, _stream_ptr(stream))
+    else:
+        st = L.salt_dot_ex(n, _dev(x), _dev(y), _dev(result), _dev(ws), nb, d, _stream_ptr(stream), _cfg(config))
+    check(st)
+    return result
+
+
+def salt_nrm2(x, n: int | None = None, result=None, ws=None, stream=None, config=None):
+    """Device scalar sqrt(sum x[i]^2)."""
+    d = dtype_code(x)
+    if n is None:
+        n = x.numel()
+    if x.numel() < n:
+        raise ValueError("tensor shorter than n")
+    result = _result_tensor(d, x.device) if result is None else result
+    ws = workspace(n, d, x.device) if ws is None else ws
+    nb = ws.numel() * ws.element_size()
+    L = lib()
+    if config is None:
+        st = L.salt_nrm2(n, _dev(x), _dev(result), _dev(ws), nb, d, _stream_ptr(stream))
+    else:
+        st = L.salt_nrm2_ex(n, _dev(x), _dev(result), _dev(ws), nb, d, _stream_ptr(stream), _cfg(config))
+    check(st)
+    return result
+
+
+# ---------------------------------------------------------------------------
+# host-only helpers
+# ---------------------------------------------------------------------------
+
+def salt_program_check(prog: Sequence[int], n_operands: int, n_scalars: int):
+    """(stack_need, n_loads) of a valid program; raises SaltError otherwise."""
+    parr, plen = _prog(prog)
+    sn, nl = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().salt_program_check(parr, plen, n_operands, n_scalars, ctypes.byref(sn), ctypes.byref(nl)))
+    return sn.value, nl.value
+
+
+def salt_program_route(prog: Sequence[int], n_operands: int, n_scalars: int) -> int:
+    """Catalogue index of the kernel a program runs on, or -1 (interpreter)."""
+    parr, plen = _prog(prog)
+    r = ctypes.c_int32()
+    check(lib().salt_program_route(parr, plen, n_operands, n_scalars, ctypes.byref(r)))
+    return r.value
+
+
+def salt_catalogue() -> list[tuple[str, list[int]]]:
+    """[(name, canonical postfix tokens)] of the ahead-of-time trees."""
+    L = lib()
+    out = []
+    for i in range(L.salt_catalogue_count()):
+        buf = (ctypes.c_uint32 * MAX_TOKENS)()
+        name = ctypes.c_char_p()
+        n = L.salt_catalogue_program(i, buf, MAX_TOKENS, ctypes.byref(name))
+        out.append((name.value.decode(), list(buf[:n])))
+    return out
+
+
+def salt_tuning_load(path: str | None = None) -> None:
+    check(lib().salt_tuning_load(path.encode() if path else None))
+
+
+def salt_tuning_lookup(kind: int, route: int, dtype: int, n: int) -> tuple[int, int, int]:
+    c = LaunchConfig()
+    check(lib().salt_tuning_lookup(kind, route, dtype, n, ctypes.byref(c)))
+    return c.as_tuple()
+
+
+def salt_version() -> int:
+    return int(lib().salt_version())
