@@ -55,7 +55,14 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libsalt.so is not built (run python -m paper_1109_1264_amd.build)")
+    # torch brings its own HIP runtime; loading it first makes libsalt bind to
+    # that same runtime, so device pointers and streams are shared. Loading
+    # libsalt first would start a second HIP runtime in the process.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes_mapped()
+    if len(runtimes) > 1:
+        raise RuntimeError("two HIP runtimes are loaded (%s): libsalt must share torch's" % sorted(runtimes))
     P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     U32P = ctypes.POINTER(ctypes.c_uint32)
     CFG = ctypes.POINTER(LaunchConfig)
@@ -85,6 +92,15 @@ def lib() -> ctypes.CDLL:
         f.restype = res
     _lib = L
     return L
+
+
+def _hip_runtimes_mapped() -> set:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as fh:
+            return {l.split()[-1] for l in fh if "libamdhip64" in l}
+    except OSError:
+        return set()
 
 
 def _status_string(s: int) -> str:
