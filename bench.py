@@ -88,6 +88,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-log2n", type=int, default=26)
+    ap.add_argument("--kernels-only", default=None,
+                    help="comma list of tree5,axpy,dot,nrm2,copy: launch only these, --steps times "
+                         "each, and print nothing else (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -136,6 +139,17 @@ def main() -> int:
             launch(k)
             if events is not None:
                 events[k][1].record()
+
+    if args.kernels_only:
+        for k in args.kernels_only.split(","):
+            for _ in range(args.steps):
+                if k == "copy":
+                    salt.salt_eval(copy, [a], [], d)
+                else:
+                    launch(k)
+            torch.cuda.synchronize()
+            log("bench: ran %s x%d" % (k, args.steps))
+        return 0
 
     for _ in range(args.warmup):
         step()

@@ -151,13 +151,14 @@ salt_status salt_nrm2_ex(int64_t n, const void *x, void *result,
 int64_t salt_reduce_tile_elems(salt_dtype dtype);
 
 /* Load a tuning table (text; one "kind route dtype log2n unroll nontemporal
- * blocks" row per line, '#' comments; kind is eval, dot or nrm2; route is a
+ * blocks" row per line, "#" comments; kind is eval, dot, nrm2 or batch; route is a
  * catalogue index or -1 for the interpreter). NULL reloads the default file
  * (SALT_TUNE_FILE, else salt_tuning.txt beside the library). Rows replace the
  * current table. Returns SALT_ERR_ARG if the file cannot be read or parsed. */
 salt_status salt_tuning_load(const char *path);
 
-/* The knobs a call would use (kind 0 eval, 1 dot, 2 nrm2). */
+/* The knobs a call would use (kind 0 eval, 1 dot, 2 nrm2, 3 batch; for a
+ * batch, n is the total number of elements). */
 salt_status salt_tuning_lookup(int32_t kind, int32_t route, salt_dtype dtype, int64_t n,
                                salt_launch_config *out);
 
@@ -171,6 +172,65 @@ int32_t salt_catalogue_program(int32_t i, uint32_t *tokens, int32_t cap, const c
  * the generic interpreter. Host only. */
 salt_status salt_program_route(const uint32_t *prog, int32_t prog_len,
                                int32_t n_operands, int32_t n_scalars, int32_t *route);
+
+/* ---- batched evaluation --------------------------------------------------
+ * Many independent evaluations of one tree, of uneven lengths, in one
+ * persistent launch: every item is cut into the reduction's fixed tiles and
+ * a grid of workgroups walks the flat list of all items' tiles. An item can
+ * also ask for dot(operands[0], operands[1]), computed from the same loaded
+ * registers (the operands are read once for both); its summation order is
+ * that of salt_dot, so the result has the same bits as salt_dot alone. */
+typedef struct {
+    int64_t n;                                /* elements (>= 0)                     */
+    const void *operands[SALT_MAX_OPERANDS];  /* device pointers, as for salt_eval   */
+    double scalars[SALT_MAX_SCALARS];
+    void *out;      /* device pointer to n elements, or NULL for no element-wise output */
+    void *dot_out;  /* device scalar (double for F64, float otherwise) for
+                     * dot(operands[0], operands[1]), or NULL */
+} salt_batch_item;
+
+typedef struct salt_batch_plan_s *salt_batch_plan;
+typedef struct salt_graph_s *salt_graph;
+
+/* Validate `count` items against one program and element type and build the
+ * host side of the descriptor table. The program must be one of the
+ * ahead-of-time trees (salt_catalogue_*), else SALT_ERR_UNSUPPORTED; an item
+ * with dot_out needs a program whose first two operands read (in postfix
+ * order) are operands[0] and operands[1]. Every check of salt_eval applies to
+ * every item. Items must not write to memory another item reads or writes.
+ * On success *plan owns host memory only; free it with
+ * salt_batch_plan_destroy. */
+salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len,
+                                   int32_t n_operands, int32_t n_scalars,
+                                   const salt_batch_item *items, int32_t count,
+                                   salt_dtype dtype, salt_batch_plan *plan);
+
+/* Device bytes the plan needs: the descriptor table (uploaded once) and the
+ * workspace (one binary64 per tile when any item has a dot, else 0), and the
+ * number of tiles. */
+salt_status salt_batch_plan_info(salt_batch_plan plan, size_t *table_bytes,
+                                 size_t *ws_bytes, int64_t *tiles);
+
+/* Copy the descriptor table into `table` (device, 256-byte aligned, at least
+ * table_bytes) on `hip_stream` and wait for the copy. The plan keeps the
+ * pointer: later launches read the table there. */
+salt_status salt_batch_upload(salt_batch_plan plan, void *table, size_t table_bytes,
+                              void *hip_stream);
+
+/* Enqueue the batched kernel (and, when any item has a dot, the per-item
+ * combine) on `hip_stream`. `workspace`: device, 8-byte aligned, >= ws_bytes
+ * (may be NULL when ws_bytes is 0). cfg NULL = tuned. */
+salt_status salt_batch_launch(salt_batch_plan plan, void *workspace, size_t ws_bytes,
+                              void *hip_stream, const salt_launch_config *cfg);
+
+/* Capture salt_batch_launch into a HIP graph (on a private stream) and
+ * instantiate it; salt_graph_launch replays it on any stream. The graph
+ * holds the table, workspace and item pointers as they are now. */
+salt_status salt_batch_graph_create(salt_batch_plan plan, void *workspace, size_t ws_bytes,
+                                    const salt_launch_config *cfg, salt_graph *graph);
+salt_status salt_graph_launch(salt_graph graph, void *hip_stream);
+void salt_graph_destroy(salt_graph graph);
+void salt_batch_plan_destroy(salt_batch_plan plan);
 
 /* Validate a program without touching the GPU. On success fills
  * *stack_need (maximum stack depth) and *n_loads (distinct operands read)

@@ -1,0 +1,159 @@
+"""Measured choice of launch knobs (unroll, non-temporal hints, grid size).
+
+The paper picks the number of instruction packages per loop by trial, few for
+small vectors and many for large ones (Sec. 4.3). Here every candidate
+(unroll x non-temporal x grid) is timed with HIP events on the launch stream
+for each (kind, tree, element type, size) and the fastest one is written to
+a tuning table that libsalt loads at start-up (``salt_tuning.txt`` beside the
+library, or ``$SALT_TUNE_FILE``). None of the knobs changes a result bit, so
+the table only moves time.
+
+    python -m paper_1109_1264_amd.autotune --out paper_1109_1264_amd/salt_tuning.txt
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+from . import salt as S
+
+KIND = {"eval": 0, "dot": 1, "nrm2": 2}
+DT_NAMES = {"f64": S.F64, "f32": S.F32, "bf16": S.BF16, "f16": S.F16}
+
+
+def _torch_dtype(d):
+    import torch
+
+    return {S.F64: torch.float64, S.F32: torch.float32, S.BF16: torch.bfloat16, S.F16: torch.float16}[d]
+
+
+def candidates(kind: str, n: int, dtype: int, cus: int):
+    unrolls = (1, 2, 4, 8) if kind == "eval" else (2, 4, 8, 16)
+    grids = [0] + [cus * k for k in (1, 2, 4, 8, 16)]
+    out = []
+    for u in unrolls:
+        for nt in (0, 1):
+            for b in grids:
+                out.append((u, nt, b))
+    return out
+
+
+def time_config(fn, cfg, reps: int, warm: int = 2) -> float:
+    """Median event time (ms) of fn(cfg) over reps launches."""
+    import torch
+
+    for _ in range(warm):
+        fn(cfg)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn(cfg)
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in ev)
+    return ts[len(ts) // 2]
+
+
+class Workload:
+    """Device buffers for one (kind, tree, dtype) at the largest size swept."""
+
+    def __init__(self, kind: str, tree: str | None, dtype: int, n_max: int):
+        import torch
+
+        self.kind, self.dtype = kind, dtype
+        td = _torch_dtype(dtype)
+        cat = dict(S.salt_catalogue())
+        self.route = -1
+        if kind == "eval":
+            self.prog = cat[tree]
+            self.route = [name for name, _ in S.salt_catalogue()].index(tree)
+            nops = 1 + max([t >> 8 for t in self.prog if t & 0xFF == S.LOAD], default=-1)
+            nsc = 1 + max([t >> 8 for t in self.prog if t & 0xFF == S.SCALAR], default=-1)
+            self.ops = [torch.rand(n_max, device="cuda").to(td) for _ in range(max(nops, 1))][:nops]
+            self.sc = [1.25] * nsc
+            self.out = torch.empty(n_max, dtype=td, device="cuda")
+            self.arrays = nops + 1
+        else:
+            self.x = torch.rand(n_max, device="cuda").to(td)
+            self.y = torch.rand(n_max, device="cuda").to(td) if kind == "dot" else self.x
+            self.ws = S.workspace(n_max, dtype)
+            self.res = torch.empty(1, dtype=torch.float64 if dtype == S.F64 else torch.float32, device="cuda")
+            self.arrays = 2 if kind == "dot" else 1
+
+    def fn(self, n: int):
+        if self.kind == "eval":
+            ops = [o[:n] for o in self.ops]
+            out = self.out[:n]
+            return lambda cfg: S.salt_eval(self.prog, ops, self.sc, out, config=cfg)
+        if self.kind == "dot":
+            x, y = self.x[:n], self.y[:n]
+            return lambda cfg: S.salt_dot(x, y, result=self.res, ws=self.ws, config=cfg)
+        x = self.x[:n]
+        return lambda cfg: S.salt_nrm2(x, result=self.res, ws=self.ws, config=cfg)
+
+
+def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbose: bool = False):
+    """Rows (kind, route, dtype, log2n, unroll, nt, blocks, best_ms, GBps)."""
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    w = Workload(kind, tree, dtype, 1 << max(log2ns))
+    rows = []
+    for l in log2ns:
+        n = 1 << l
+        fn = w.fn(n)
+        reps_l = reps if l >= 20 else reps * 3
+        best = None
+        for cfg in candidates(kind, n, dtype, cus):
+            t = time_config(fn, cfg, reps_l)
+            if best is None or t < best[0]:
+                best = (t, cfg)
+        t, (u, nt, b) = best
+        gbps = w.arrays * n * S.ELEM_BYTES[dtype] / (t * 1e-3) / 1e9
+        rows.append((kind, w.route, dtype, l, u, nt, b, t, gbps))
+        if verbose:
+            print("tuned %s %s %s 2^%d: unroll=%d nt=%d blocks=%d %.4f ms %.0f GB/s"
+                  % (kind, tree or "", S.DTYPE_NAMES[dtype], l, u, nt, b, t, gbps), file=sys.stderr, flush=True)
+    return rows
+
+
+def write_table(rows, path: str) -> None:
+    with open(path, "w") as fh:
+        fh.write("# libsalt tuning table, written by paper_1109_1264_amd.autotune\n")
+        fh.write("# kind route dtype log2n unroll nontemporal blocks   # best ms, GB/s\n")
+        for kind, route, dtype, l, u, nt, b, t, g in rows:
+            fh.write("%s %d %d %d %d %d %d   # %.4f ms %.0f GB/s\n" % (kind, route, dtype, l, u, nt, b, t, g))
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "salt_tuning.txt"))
+    ap.add_argument("--trees", default="copy,scale,fig1,axpy,tree5,abc,t4,t5")
+    ap.add_argument("--dtypes", default="f64,f32,bf16,f16")
+    ap.add_argument("--log2n", default="10-28")
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--json", default=None, help="also write all rows as JSON here")
+    args = ap.parse_args(argv)
+    lo, hi = (int(v) for v in args.log2n.split("-"))
+    t0 = time.time()
+    rows = []
+    for dname in args.dtypes.split(","):
+        d = DT_NAMES[dname]
+        # keep the largest size within memory: 2^28 elements of any type fit
+        for kind in ("dot", "nrm2"):
+            rows += tune(kind, None, d, range(lo, hi + 1), args.reps, verbose=True)
+        for tree in args.trees.split(","):
+            rows += tune("eval", tree, d, range(lo, hi + 1), args.reps, verbose=True)
+    write_table(rows, args.out)
+    if args.json:
+        with open(args.json, "w") as fh:
+            json.dump(rows, fh)
+    print("wrote %d rows to %s in %.0f s" % (len(rows), args.out, time.time() - t0), file=sys.stderr)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

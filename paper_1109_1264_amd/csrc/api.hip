@@ -13,10 +13,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <mutex>
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "expr.hpp"
 #include "launch.hpp"
 #include "program.hpp"
@@ -76,7 +78,7 @@ int route_of(const Program &p) {
 }
 
 // ---- tuning table ------------------------------------------------------------
-enum Kind { kEval = 0, kDot = 1, kNrm2 = 2 };
+enum Kind { kEval = 0, kDot = 1, kNrm2 = 2, kBatch = 3 };
 
 struct TuneRow {
     int kind, route, dtype, log2n;
@@ -118,7 +120,7 @@ bool parse_tune(const std::string &path, std::vector<TuneRow> &rows, std::string
         if (got <= 0) continue;
         TuneRow r;
         r.kind = !std::strcmp(kind, "eval") ? kEval : !std::strcmp(kind, "dot") ? kDot
-               : !std::strcmp(kind, "nrm2") ? kNrm2 : -1;
+               : !std::strcmp(kind, "nrm2") ? kNrm2 : !std::strcmp(kind, "batch") ? kBatch : -1;
         if (got != 7 || r.kind < 0 || !dtype_ok(dtype) || log2n < 0 || log2n > 62 || nt < 0 || nt > 1 || blocks < 0) {
             if (why) *why = path + ": bad row at line " + std::to_string(lineno);
             ok = false;
@@ -155,6 +157,7 @@ salt_launch_config default_cfg(int kind, int dtype, int64_t n, int n_arrays) {
     salt_launch_config c;
     const double bytes = (double)n * (double)esize(dtype) * n_arrays;
     c.unroll = kind == kEval ? 4 : 8;
+    if (kind == kEval && bytes >= 256.0 * 1024 * 1024) c.unroll = n_arrays <= 3 ? 1 : 4;
     c.nontemporal = bytes >= 256.0 * 1024 * 1024 ? 1 : 0;
     c.blocks = 0;
     return c;
@@ -280,10 +283,61 @@ salt_status reduce_impl(int64_t n, const void *x, const void *y, void *result, v
     return device_status(launch_reduce(L, dtype));
 }
 
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
 }  // namespace
 }  // namespace salt
 
+struct salt_batch_plan_s {
+    int route = -1, dtype = 0, count = 0;
+    int64_t total_tiles = 0, total_elems = 0;
+    bool any_dot = false;
+    std::vector<salt::DevItem> items;
+    std::vector<int32_t> tile_item;
+    size_t table_bytes = 0, ws_bytes = 0;
+    void *table = nullptr;
+};
+
+struct salt_graph_s {
+    hipGraphExec_t exec = nullptr;
+};
+
 using namespace salt;
+
+namespace salt {
+namespace {
+
+salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, void *stream,
+                              const salt_launch_config *cfg) {
+    if (!plan) return fail(SALT_ERR_ARG, "plan is NULL");
+    if (!plan->table) return fail(SALT_ERR_ARG, "plan has not been uploaded");
+    if (plan->ws_bytes > 0) {
+        if (!ws) return fail(SALT_ERR_WORKSPACE, "workspace is NULL");
+        if (((uintptr_t)ws & 7u) != 0) return fail(SALT_ERR_WORKSPACE, "workspace not 8-byte aligned");
+        if (ws_bytes < plan->ws_bytes) return fail(SALT_ERR_WORKSPACE, "workspace too small");
+    }
+    salt_launch_config c;
+    salt_status s = resolve(cfg, lookup(kBatch, plan->route, plan->dtype, plan->total_elems, 4), false, &c);
+    if (s != SALT_OK) return s;
+    if (plan->count == 0) return SALT_OK;
+    BatchFn fn = catalogue_batch_launcher(plan->route, plan->dtype);
+    if (!fn) return fail(SALT_ERR_UNSUPPORTED, "no batched kernel for this tree and dtype");
+    BatchLaunch L;
+    L.items = (const DevItem *)plan->table;
+    L.tile_item = (const int32_t *)((const char *)plan->table + sizeof(DevItem) * plan->count);
+    L.total_tiles = plan->total_tiles;
+    L.count = plan->count;
+    L.any_dot = plan->any_dot ? 1 : 0;
+    L.ws = (double *)ws;
+    L.unroll = c.unroll;
+    L.nontemporal = c.nontemporal;
+    L.blocks = c.blocks;
+    L.stream = stream;
+    return device_status((hipError_t)fn(L));
+}
+
+}  // namespace
+}  // namespace salt
 
 extern "C" {
 
@@ -340,6 +394,173 @@ salt_status salt_nrm2_ex(int64_t n, const void *x, void *result, void *workspace
     return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, cfg, true);
 }
 
+salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len, int32_t n_operands,
+                                   int32_t n_scalars, const salt_batch_item *items, int32_t count,
+                                   salt_dtype dtype, salt_batch_plan *plan) {
+    if (!plan) return fail(SALT_ERR_ARG, "plan pointer is NULL");
+    *plan = nullptr;
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    if (count < 0) return fail(SALT_ERR_ARG, "negative item count");
+    if (count > 0 && !items) return fail(SALT_ERR_ARG, "item array is NULL");
+    Program p;
+    std::string why;
+    salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, why);
+    const int route = route_of(p);
+    if (route == kRouteGeneric)
+        return fail(SALT_ERR_UNSUPPORTED, "batched launches need a tree with an ahead-of-time kernel");
+    const int64_t T = reduce_tile_elems(dtype);
+    auto *pl = new (std::nothrow) salt_batch_plan_s;
+    if (!pl) return fail(SALT_ERR_ARG, "out of host memory");
+    pl->route = route;
+    pl->dtype = dtype;
+    pl->count = count;
+    const size_t es = esize(dtype);
+    int64_t tiles = 0;
+    try {
+        pl->items.resize(count);
+        for (int i = 0; i < count; ++i) {
+            const salt_batch_item &it = items[i];
+            const std::string at = "item " + std::to_string(i) + ": ";
+            if (it.n < 0 || (uint64_t)it.n > (uint64_t)INT64_MAX / 16) {
+                delete pl;
+                return fail(SALT_ERR_ARG, at + "bad length");
+            }
+            DevItem d;
+            std::memset(&d, 0, sizeof d);
+            d.n = it.n;
+            d.tile_begin = tiles;
+            bool vec = !it.out || aligned16(it.out);
+            const size_t bytes = (size_t)it.n * es;
+            for (int k = 0; k < p.n_loads; ++k) {
+                const void *a = it.operands[p.op_map[k]];
+                if (it.n > 0 && !a) {
+                    delete pl;
+                    return fail(SALT_ERR_ARG, at + "operand " + std::to_string(p.op_map[k]) + " is NULL");
+                }
+                if (it.out && it.n > 0 && partial_overlap(a, it.out, bytes)) {
+                    delete pl;
+                    return fail(SALT_ERR_ARG, at + "output partially overlaps an operand");
+                }
+                d.ops[k] = a;
+                vec = vec && aligned16(a);
+            }
+            for (int j = 0; j < p.n_scal; ++j) {
+                d.sc64[j] = it.scalars[p.sc_map[j]];
+                d.sc32[j] = (float)it.scalars[p.sc_map[j]];
+            }
+            d.vec = vec ? 1 : 0;
+            d.out = it.n > 0 ? it.out : nullptr;
+            d.dot_out = it.dot_out;
+            if (it.dot_out) {
+                if (p.n_loads < 2 || p.op_map[0] != 0 || p.op_map[1] != 1) {
+                    delete pl;
+                    return fail(SALT_ERR_UNSUPPORTED,
+                                at + "dot needs a program whose first two operands read are operands 0 and 1");
+                }
+                pl->any_dot = true;
+            }
+            const int64_t nt = (it.n + T - 1) / T;
+            if (tiles + nt > (int64_t)INT32_MAX) {
+                delete pl;
+                return fail(SALT_ERR_UNSUPPORTED, "too many tiles in one batch");
+            }
+            for (int64_t t = 0; t < nt; ++t) pl->tile_item.push_back(i);
+            tiles += nt;
+            pl->total_elems += it.n;
+            pl->items[i] = d;
+        }
+    } catch (...) {
+        delete pl;
+        return fail(SALT_ERR_ARG, "out of host memory");
+    }
+    pl->total_tiles = tiles;
+    pl->table_bytes = round_up(sizeof(DevItem) * (size_t)count + sizeof(int32_t) * (size_t)tiles, 256);
+    pl->ws_bytes = pl->any_dot ? sizeof(double) * (size_t)tiles : 0;
+    *plan = pl;
+    return SALT_OK;
+}
+
+salt_status salt_batch_plan_info(salt_batch_plan plan, size_t *table_bytes, size_t *ws_bytes, int64_t *tiles) {
+    if (!plan) return fail(SALT_ERR_ARG, "plan is NULL");
+    if (table_bytes) *table_bytes = plan->table_bytes;
+    if (ws_bytes) *ws_bytes = plan->ws_bytes;
+    if (tiles) *tiles = plan->total_tiles;
+    return SALT_OK;
+}
+
+salt_status salt_batch_upload(salt_batch_plan plan, void *table, size_t table_bytes, void *hip_stream) {
+    if (!plan) return fail(SALT_ERR_ARG, "plan is NULL");
+    if (!table) return fail(SALT_ERR_ARG, "table pointer is NULL");
+    if (((uintptr_t)table & 255u) != 0) return fail(SALT_ERR_ARG, "table not 256-byte aligned");
+    if (table_bytes < plan->table_bytes) return fail(SALT_ERR_ARG, "table buffer too small");
+    std::vector<char> host(plan->table_bytes, 0);
+    std::memcpy(host.data(), plan->items.data(), sizeof(DevItem) * plan->items.size());
+    std::memcpy(host.data() + sizeof(DevItem) * plan->items.size(), plan->tile_item.data(),
+                sizeof(int32_t) * plan->tile_item.size());
+    if (plan->table_bytes > 0) {
+        hipError_t e = hipMemcpyAsync(table, host.data(), plan->table_bytes, hipMemcpyHostToDevice,
+                                      (hipStream_t)hip_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
+        if (e != hipSuccess) return device_status(e);
+    }
+    plan->table = table;
+    return SALT_OK;
+}
+
+salt_status salt_batch_launch(salt_batch_plan plan, void *workspace, size_t ws_bytes, void *hip_stream,
+                              const salt_launch_config *cfg) {
+    return batch_launch_impl(plan, workspace, ws_bytes, hip_stream, cfg);
+}
+
+salt_status salt_batch_graph_create(salt_batch_plan plan, void *workspace, size_t ws_bytes,
+                                    const salt_launch_config *cfg, salt_graph *graph) {
+    if (!graph) return fail(SALT_ERR_ARG, "graph pointer is NULL");
+    *graph = nullptr;
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return device_status(e);
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return device_status(e);
+    }
+    const salt_status st = batch_launch_impl(plan, workspace, ws_bytes, s, cfg);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    (void)hipStreamDestroy(s);
+    if (st != SALT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return device_status(e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return device_status(e);
+    auto *gr = new (std::nothrow) salt_graph_s;
+    if (!gr) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(SALT_ERR_ARG, "out of host memory");
+    }
+    gr->exec = exec;
+    *graph = gr;
+    return SALT_OK;
+}
+
+salt_status salt_graph_launch(salt_graph graph, void *hip_stream) {
+    if (!graph || !graph->exec) return fail(SALT_ERR_ARG, "graph is NULL");
+    return device_status(hipGraphLaunch(graph->exec, (hipStream_t)hip_stream));
+}
+
+void salt_graph_destroy(salt_graph graph) {
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    delete graph;
+}
+
+void salt_batch_plan_destroy(salt_batch_plan plan) { delete plan; }
+
 salt_status salt_tuning_load(const char *path) {
     std::vector<TuneRow> rows;
     std::string why;
@@ -353,8 +574,8 @@ salt_status salt_tuning_load(const char *path) {
 
 salt_status salt_tuning_lookup(int32_t kind, int32_t route, salt_dtype dtype, int64_t n,
                                salt_launch_config *out) {
-    if (!out || kind < 0 || kind > 2 || !dtype_ok(dtype)) return fail(SALT_ERR_ARG, "bad lookup arguments");
-    *out = lookup(kind, route, dtype, n, kind == kNrm2 ? 1 : 2);
+    if (!out || kind < 0 || kind > 3 || !dtype_ok(dtype)) return fail(SALT_ERR_ARG, "bad lookup arguments");
+    *out = lookup(kind, route, dtype, n, kind == kNrm2 ? 1 : kind == kBatch ? 4 : 2);
     return SALT_OK;
 }
 

@@ -1,0 +1,46 @@
+// batch.hpp -- the device descriptor of one batched item, shared by the host
+// planner (api) and the batched kernels.
+#pragma once
+
+#include <cstdint>
+
+#include "salt.h"
+
+namespace salt {
+
+// One item of a batched launch, in the canonical operand order of the
+// batch's program. 256 bytes, so the table is an array of aligned records.
+struct alignas(16) DevItem {
+    int64_t n;
+    int64_t tile_begin;  // first global tile of this item
+    int32_t vec;         // every array of the item is 16-byte aligned
+    int32_t pad0;
+    const void *ops[SALT_MAX_OPERANDS];
+    double sc64[SALT_MAX_SCALARS];  // scalars rounded to binary64 ...
+    float sc32[SALT_MAX_SCALARS];   // ... and to binary32 (once, on the host)
+    void *out;      // element-wise output, or null
+    void *dot_out;  // dot of canonical operands 0 and 1, or null
+    int64_t pad1[7];
+};
+static_assert(sizeof(DevItem) == 256, "descriptor layout");
+
+// Host-side launch of the batched kernels for one (tree, dtype).
+struct BatchLaunch {
+    const DevItem *items;
+    const int32_t *tile_item;  // global tile -> item
+    int64_t total_tiles;
+    int32_t count;
+    int32_t any_dot;
+    double *ws;  // one binary64 partial per global tile (when any_dot)
+    int32_t unroll;
+    int32_t nontemporal;
+    int64_t blocks;
+    void *stream;
+};
+
+using BatchFn = int (*)(const BatchLaunch &);  // returns a hipError_t
+BatchFn catalogue_batch_launcher(int id, int dtype);
+// Number of distinct operands the catalogue tree reads (-1: bad id).
+int catalogue_loads(int id);
+
+}  // namespace salt

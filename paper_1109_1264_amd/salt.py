@@ -45,6 +45,13 @@ class LaunchConfig(ctypes.Structure):
         return (self.unroll, self.nontemporal, self.blocks)
 
 
+class BatchItem(ctypes.Structure):
+    """salt_batch_item."""
+    _fields_ = [("n", ctypes.c_int64), ("operands", ctypes.c_void_p * MAX_OPERANDS),
+                ("scalars", ctypes.c_double * MAX_SCALARS), ("out", ctypes.c_void_p),
+                ("dot_out", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -85,6 +92,15 @@ def lib() -> ctypes.CDLL:
         "salt_status_string": ([I32], ctypes.c_char_p),
         "salt_last_error": ([], ctypes.c_char_p),
         "salt_version": ([], I32),
+        "salt_batch_plan_create": ([U32P, I32, I32, I32, ctypes.POINTER(BatchItem), I32, I32,
+                                    ctypes.POINTER(P)], I32),
+        "salt_batch_plan_info": ([P, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(I64)], I32),
+        "salt_batch_upload": ([P, P, SZ, P], I32),
+        "salt_batch_launch": ([P, P, SZ, P, CFG], I32),
+        "salt_batch_graph_create": ([P, P, SZ, CFG, ctypes.POINTER(P)], I32),
+        "salt_graph_launch": ([P, P], I32),
+        "salt_graph_destroy": ([P], None),
+        "salt_batch_plan_destroy": ([P], None),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
