@@ -1,22 +1,35 @@
 """Benchmark of the SALT hot path on one MI355X.
 
 One step = one pass of the hot path over one batch of HBM-resident synthetic
-vectors (BLAS-1 sweep at its largest size, n = 2^28, binary64):
+vectors (the BLAS-1 sweep at its largest size, n = 2^28, binary64):
     d = a*b + c*e - f      (fused 5-operand tree, salt_eval)
     d = alpha*a + d        (salt_axpy, in place)
     dot(a, b)              (salt_dot)
     nrm2(c)                (salt_nrm2)
 `value` = algorithmic bytes of the step (inputs read once + outputs written
-once) / wall time per step, in GB/s. Per-kernel durations come from HIP
-events recorded on the launch stream inside the timed region.
+once: 96 B per element) / wall time per step, in GB/s. Per-kernel durations
+are HIP events recorded on the launch stream around every launch inside the
+timed region.
+
+The same JSON line also reports the three systems layers beside the plain
+binary64 kernels (each measured after the timed step):
+    precision: dot / nrm2 at n = 2^26, storage FP64 / FP32 / BF16, with the
+               error against the binary64 oracle per result;
+    batched:   4096 lognormal-length instances of alpha*a + (b - c) plus
+               dot(a, b) in one persistent launch replayed from a HIP graph,
+               against 4096 separate launches and one binary64 kernel;
+    served:    Poisson request streams at fractions of the measured
+               saturation rate, p50 / p99 latency and throughput.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
+                    [--sections main,precision,batched,served]
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -26,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "achieved HBM GB/s (% of peak) on fused vector exprs; served p50/p99 latency"
+PROFILE_PMC = os.path.join(ROOT, "profiles", "pmc_tree5_f64_n2p28.json")
 
 
 def log(*a):
@@ -43,18 +57,36 @@ def kernel_source_hash() -> str:
 def traffic_from_profile(n_elems: int):
     """HBM bytes per launch of the tree kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "pmc_tree5_f64_n2p28.json")
-    if not os.path.exists(path):
+    if not os.path.exists(PROFILE_PMC):
         return None
-    with open(path) as fh:
+    with open(PROFILE_PMC) as fh:
         d = json.load(fh)
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n") != n_elems:
         return None
     return d.get("traffic_bytes_per_launch")
 
 
+def event_ms(fn, reps: int, warm: int = 2) -> float:
+    """Mean duration (ms) of fn() from HIP events on the current stream."""
+    import numpy as np
+    import torch
+
+    for _ in range(warm):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample of the step
+# ---------------------------------------------------------------------------
+
 def cpu_baseline(log2n_sample: int, reps: int = 3):
-    """The oracle (plain C, one thread) on a bounded sample of the step."""
     import numpy as np
 
     import oracle
@@ -75,29 +107,16 @@ def cpu_baseline(log2n_sample: int, reps: int = 3):
     t = float(np.median(times))
     return {"value": round(96.0 * n / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": "one step of the same hot path (tree eval, axpy, Dot2 dot, Dot2 nrm2) on n=2^%d "
-                      "binary64 elements, median of %d, single-threaded plain C" % (log2n_sample, reps),
+                      "binary64 elements (of the 2^28 in the GPU step), median of %d runs, "
+                      "single-threaded plain C" % (log2n_sample, reps),
             "seconds_per_step": round(t, 4)}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--cpu-log2n", type=int, default=26)
-    ap.add_argument("--kernels-only", default=None,
-                    help="comma list of tree5,axpy,dot,nrm2,copy: launch only these, --steps times "
-                         "each, and print nothing else (for counter collection)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(element-wise work shards by index range and dot/nrm2 need one 8-byte "
-              "combine; see the design notes). Run with --gpus 1.", file=sys.stderr)
-        return 2
+# ---------------------------------------------------------------------------
+# main step (BLAS-1 sweep, largest size)
+# ---------------------------------------------------------------------------
 
+def section_main(args, out):
     import numpy as np
     import torch
 
@@ -105,7 +124,6 @@ def main() -> int:
     from paper_1109_1264_amd import workloads
 
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     n = 1 << args.log2n
     seed = workloads.sweep_seed(n)
     log("bench: generating 5 x %d binary64 operands on the device (seed %d)" % (n, seed))
@@ -129,8 +147,18 @@ def main() -> int:
             salt.salt_axpy(alpha, a, d)
         elif k == "dot":
             salt.salt_dot(a, b, result=r_dot, ws=ws)
-        else:
+        elif k == "nrm2":
             salt.salt_nrm2(c, result=r_nrm, ws=ws)
+        else:
+            salt.salt_eval(copy, [a], [], d)
+
+    if args.kernels_only:
+        for k in args.kernels_only.split(","):
+            for _ in range(args.steps):
+                launch(k)
+            torch.cuda.synchronize()
+            log("bench: ran %s x%d" % (k, args.steps))
+        return None
 
     def step(events=None):
         for k in names:
@@ -140,22 +168,9 @@ def main() -> int:
             if events is not None:
                 events[k][1].record()
 
-    if args.kernels_only:
-        for k in args.kernels_only.split(","):
-            for _ in range(args.steps):
-                if k == "copy":
-                    salt.salt_eval(copy, [a], [], d)
-                else:
-                    launch(k)
-            torch.cuda.synchronize()
-            log("bench: ran %s x%d" % (k, args.steps))
-        return 0
-
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-
-    # timed region: wall clock over K steps, events around every launch
     ev = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in names}
           for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -164,61 +179,40 @@ def main() -> int:
         step(ev[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = 1e3 * wall / args.steps
     per = {k: float(np.mean([ev[s][k][0].elapsed_time(ev[s][k][1]) for s in range(args.steps)])) for k in names}
     step_bytes = sum(bytes_per_elem.values()) * n
     value = step_bytes / (wall / args.steps) / 1e9
 
-    # copy kernel (d = a) as the attainable-bandwidth ceiling, same machinery
-    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
-    for s0, s1 in cev:
-        s0.record()
-        salt.salt_eval(copy, [a], [], d)
-        s1.record()
-    torch.cuda.synchronize()
-    copy_ms = float(np.mean([s0.elapsed_time(s1) for s0, s1 in cev[2:]]))
+    copy_ms = event_ms(lambda: launch("copy"), 20)
     copy_gbps = 16.0 * n / (copy_ms * 1e-3) / 1e9
-
     kernels = {k: {"avg_ms": round(per[k], 4), "GBps": round(bytes_per_elem[k] * n / (per[k] * 1e-3) / 1e9, 1),
-                   "bytes_per_elem": bytes_per_elem[k]} for k in names}
-    dom = "tree5"
-    achieved = bytes_per_elem[dom] * n / (per[dom] * 1e-3) / 1e9
-    traffic = traffic_from_profile(n)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "k_eval_tree<tree5, f64> (d = a*b + c*e - f)",
-                "algorithmic_bytes_per_launch": bytes_per_elem[dom] * n}
-
-    parity = None
-    if not args.no_parity:
-        parity = check_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("bench: timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(args.cpu_log2n)
-
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
+                   "bytes_per_elem": bytes_per_elem[k],
+                   "launch_config": salt.salt_tuning_lookup(0 if k in ("tree5", "axpy") else (1 if k == "dot" else 2),
+                                                            {"tree5": 4, "axpy": 3}.get(k, -1), salt.F64, n)}
+               for k in names}
+    achieved = bytes_per_elem["tree5"] * n / (per["tree5"] * 1e-3) / 1e9
+    out.update({
+        "value": round(value, 1), "ms_per_step": round(1e3 * wall / args.steps, 4),
         "config": {"workload": "BLAS-1 sweep, largest size: d=a*b+c*e-f, y=alpha*x+y, dot(x,y), nrm2(x); "
                                "binary64, n=2^%d, uniform[-1,1) operands resident in HBM" % args.log2n,
                    "n": n, "seed": seed, "alpha": alpha, "step_bytes": step_bytes},
         "pct_of_hbm_peak": round(100.0 * value / HBM_PEAK_GBPS, 2),
-        "roofline": roofline,
-        "cpu_baseline": cpu,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_from_profile(n),
+                     "kernel": "k_eval_tree<tree5, f64> (d = a*b + c*e - f)",
+                     "algorithmic_bytes_per_launch": bytes_per_elem["tree5"] * n},
         "kernels": kernels,
         "copy_ceiling": {"avg_ms": round(copy_ms, 4), "GBps": round(copy_gbps, 1),
                          "pct_of_hbm_peak": round(100 * copy_gbps / HBM_PEAK_GBPS, 2)},
-        "parity": parity,
-    }
-    print(json.dumps(out), flush=True)
-    return 0
+    })
+    if not args.no_parity:
+        out["parity"] = main_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5)
+    del a, b, c, e, f, d
+    torch.cuda.empty_cache()
+    return out
 
 
-def check_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5):
+def main_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5):
     """Sampled bit-exact check of the tree kernel and full-length tolerance
     checks of dot / nrm2 against the oracle, at the benchmarked size."""
     import numpy as np
@@ -247,6 +241,219 @@ def check_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5):
     return {"tree5_sampled_bit_exact": eval_ok, "samples": int(len(idx)),
             "dot_rel_err": dot_err, "nrm2_rel_err": nrm_err, "tol": 1e-13,
             "ok": bool(eval_ok and dot_err <= 1e-13 and nrm_err <= 1e-13)}
+
+
+# ---------------------------------------------------------------------------
+# precision layer
+# ---------------------------------------------------------------------------
+
+def section_precision(args):
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    n = 1 << 26
+    log("bench: precision layer, n = 2^26")
+    x64, y64 = workloads.ill_conditioned(n, workloads.SEED_PRECISION)
+    exact_dot, abs_dot = oracle.dot2(x64, y64)
+    exact_nrm = oracle.nrm2(x64)
+    rows = {}
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+    for name in ("f64", "f32", "bf16"):
+        code = {"f64": salt.F64, "f32": salt.F32, "bf16": salt.BF16}[name]
+        xs, ys = workloads.store(x64, name), workloads.store(y64, name)
+        if name == "bf16":
+            dx = torch.from_numpy(xs.view(np.int16)).view(torch.bfloat16).cuda()
+            dy = torch.from_numpy(ys.view(np.int16)).view(torch.bfloat16).cuda()
+        else:
+            dx, dy = torch.from_numpy(xs).cuda(), torch.from_numpy(ys).cuda()
+        ws = salt.workspace(n, code)
+        r1 = torch.empty(1, dtype=torch.float64 if name == "f64" else torch.float32, device="cuda")
+        r2 = torch.empty_like(r1)
+        t_dot = event_ms(lambda: salt.salt_dot(dx, dy, result=r1, ws=ws), 20)
+        t_nrm = event_ms(lambda: salt.salt_nrm2(dx, result=r2, ws=ws), 20)
+        torch.cuda.synchronize()
+        got_dot, got_nrm = float(r1.item()), float(r2.item())
+        wx, wy = oracle.widen(xs, name), oracle.widen(ys, name)
+        q_dot, q_abs = oracle.dot2(wx, wy)
+        q_nrm = oracle.nrm2(wx)
+        es = {"f64": 8, "f32": 4, "bf16": 2}[name]
+        rows[name] = {
+            "dot_ms": round(t_dot, 4), "dot_GBps": round(2 * es * n / (t_dot * 1e-3) / 1e9, 1),
+            "nrm2_ms": round(t_nrm, 4), "nrm2_GBps": round(es * n / (t_nrm * 1e-3) / 1e9, 1),
+            "accumulation": "binary64 fma" if name == "f64" else
+                            ("compensated binary32 (TwoProduct+TwoSum)" if name == "f32" else
+                             "compensated binary32 (exact products, TwoSum)") + ", binary64 combine",
+            # (i) end to end, including storage rounding, vs the binary64 data
+            "dot_err_vs_f64_data": abs(got_dot - exact_dot) / abs_dot,
+            "nrm2_err_vs_f64_data": abs(got_nrm - exact_nrm) / exact_nrm,
+            # (ii) accumulation only, vs Dot2 on the stored values (the tolerance check)
+            "dot_err_vs_stored": abs(got_dot - q_dot) / q_abs,
+            "nrm2_err_vs_stored": abs(got_nrm - q_nrm) / q_nrm,
+            "tol": oracle.TOL[name],
+        }
+        rows[name]["within_tol"] = bool(rows[name]["dot_err_vs_stored"] <= oracle.TOL[name]
+                                        and rows[name]["nrm2_err_vs_stored"] <= oracle.TOL[name])
+        del dx, dy, ws
+        torch.cuda.empty_cache()
+    return {"n": n, "inputs": "random sign, log10|x| ~ U[-4,4] (seed 3000), stored with RNE",
+            "errors_are": "relative to sum|x_i y_i| (dot) or to the norm (nrm2)", "by_storage": rows}
+
+
+# ---------------------------------------------------------------------------
+# batched layer
+# ---------------------------------------------------------------------------
+
+def section_batched(args):
+    import numpy as np
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+    from paper_1109_1264_amd.batch import Batch
+
+    lengths = workloads.batch_lengths(4096, seed=workloads.SEED_BATCHED)
+    total = int(lengths.sum())
+    log("bench: batched layer, 4096 instances, %d elements" % total)
+    offs = np.zeros(len(lengths) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum((lengths + 63) // 64 * 64)
+    cap = int(offs[-1])
+    a, b, c = workloads.uniform_device(cap, "f32", workloads.SEED_BATCHED, 3)
+    d = torch.empty(cap, dtype=torch.float32, device="cuda")
+    dots = torch.empty(len(lengths), dtype=torch.float32, device="cuda")
+    rng = np.random.Generator(np.random.PCG64(workloads.SEED_BATCHED + 1))
+    alphas = rng.uniform(0.5, 2.0, len(lengths))
+    T = salt.token
+    abc = [T(salt.SCALAR, 0), T(salt.LOAD, 0), T(salt.MUL), T(salt.LOAD, 1), T(salt.LOAD, 2), T(salt.SUB),
+           T(salt.ADD)]
+    items = []
+    for k, n in enumerate(lengths):
+        s, e = int(offs[k]), int(offs[k]) + int(n)
+        items.append({"n": int(n), "operands": [a[s:e], b[s:e], c[s:e]], "scalars": [float(alphas[k])],
+                      "out": d[s:e], "dot_out": dots[k:k + 1]})
+    bt = Batch(abc, items, salt.F32)
+    g = bt.graph()
+    alg_bytes = 16 * total + 8 * bt.tiles
+    t_graph = event_ms(g.launch, 20)
+    # the same work as 4096 separate eval + dot calls
+    ws = salt.workspace(1 << 20, salt.F32)
+
+    def separate():
+        for k, it in enumerate(items):
+            salt.salt_eval(abc, it["operands"], it["scalars"], it["out"])
+            salt.salt_dot(it["operands"][0], it["operands"][1], result=it["dot_out"], ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    separate()
+    torch.cuda.synchronize()
+    t_sep = 1e3 * (time.perf_counter() - t0)
+    # one plain binary64 kernel over the same number of elements
+    a64, b64, c64 = workloads.uniform_device(total, "f64", workloads.SEED_BATCHED, 3)
+    d64 = torch.empty(total, dtype=torch.float64, device="cuda")
+    r64 = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws64 = salt.workspace(total, salt.F64)
+
+    def plain64():
+        salt.salt_eval(abc, [a64, b64, c64], [1.25], d64)
+        salt.salt_dot(a64, b64, result=r64, ws=ws64)
+    t_64 = event_ms(plain64, 10)
+    res = {"instances": len(lengths), "elements": total, "tiles": bt.tiles,
+           "length_stats": {"min": int(lengths.min()), "median": int(np.median(lengths)),
+                            "max": int(lengths.max()), "sigma_ln": 1.5},
+           "graph_ms": round(t_graph, 4), "graph_GBps": round(alg_bytes / (t_graph * 1e-3) / 1e9, 1),
+           "launch_config": salt.salt_tuning_lookup(3, 5, salt.F32, total),
+           "separate_launches_ms": round(t_sep, 3), "speedup_vs_separate": round(t_sep / t_graph, 1),
+           "plain_f64_one_kernel_ms": round(t_64, 4),
+           "plain_f64_GBps": round((32 * total + 16 * total) / (t_64 * 1e-3) / 1e9, 1)}
+    g.close()
+    bt.close()
+    return res
+
+
+# ---------------------------------------------------------------------------
+# serving layer
+# ---------------------------------------------------------------------------
+
+def section_served(args):
+    import torch
+
+    from paper_1109_1264_amd import serve as V
+    from paper_1109_1264_amd import workloads
+
+    log("bench: served layer, building the resident pool")
+    pool = V.Pool(args.pool_gb << 30, seed=workloads.SEED_SERVED)
+    arena, table = V.default_buffers(arena_bytes=8 << 30, table_bytes=64 << 20)
+    out = {"pool_GB": args.pool_gb, "arena_GB": 8, "trees": list(V.TREES),
+           "dtype_mix": dict(V.MIX), "lengths": "log-uniform 2^8..2^24"}
+    # saturation: every request present at t = 0
+    trace, meta = V.make_trace(pool, args.served_requests, seed=workloads.SEED_SERVED, rate=None)
+    sat = V.summarize(V.serve(trace, arena, table), meta)
+    out["saturation"] = sat
+    rate_sat = sat["throughput_rps"]
+    levels = {}
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        trace, meta = V.make_trace(pool, args.served_requests, seed=workloads.SEED_SERVED + int(100 * frac),
+                                   rate=frac * rate_sat)
+        levels[str(frac)] = V.summarize(V.serve(trace, arena, table), meta)
+        log("bench: served at %.2f of saturation: %s" % (frac, levels[str(frac)]))
+    out["poisson"] = levels
+    # the same stream with every request in binary64
+    trace, meta = V.make_trace(pool, args.served_requests, seed=workloads.SEED_SERVED + 50, rate=0.5 * rate_sat,
+                               fp64_only=True, mix=(("f64", 1.0),))
+    out["poisson_0.5_all_f64"] = V.summarize(V.serve(trace, arena, table), meta)
+    del pool, arena, table
+    torch.cuda.empty_cache()
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--sections", default="main,precision,batched,served")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-log2n", type=int, default=26)
+    ap.add_argument("--pool-gb", type=int, default=64)
+    ap.add_argument("--served-requests", type=int, default=10000)
+    ap.add_argument("--kernels-only", default=None,
+                    help="comma list of tree5,axpy,dot,nrm2,copy: launch only these, --steps times "
+                         "each, and print nothing (for counter collection)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(element-wise work shards by index range and dot/nrm2 need one 8-byte "
+              "combine; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    torch.cuda.set_device(0)
+    out = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    sections = args.sections.split(",")
+    if args.kernels_only:
+        section_main(args, out)
+        return 0
+    if "main" in sections:
+        section_main(args, out)
+    if "precision" in sections:
+        out["precision"] = section_precision(args)
+    if "batched" in sections:
+        out["batched"] = section_batched(args)
+    if "served" in sections:
+        out["served"] = section_served(args)
+    if not args.no_cpu_baseline and "main" in sections:
+        log("bench: timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_log2n)
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 if __name__ == "__main__":

@@ -232,6 +232,55 @@ salt_status salt_graph_launch(salt_graph graph, void *hip_stream);
 void salt_graph_destroy(salt_graph graph);
 void salt_batch_plan_destroy(salt_batch_plan plan);
 
+/* ---- serving ---------------------------------------------------------------
+ * A request loop over expression evaluations whose operands stay resident
+ * in device memory. Requests arrive over time (open loop, from a trace);
+ * each is admitted when a slot is free and its output fits in the output
+ * arena (first-fit; memory-based admission, FIFO order); admitted requests
+ * are gathered into batched launches (one per tree and element type in the
+ * batch) on one of several streams as soon as a stream can take more work,
+ * so requests that arrive while others run are admitted and overlap with
+ * them on the device (continuous batching). Completion times are the GPU
+ * events of the batch, mapped to the host clock. Everything runs on the
+ * calling thread; the call returns when every request has completed or been
+ * rejected. */
+typedef struct {
+    void *arena;             /* device memory for outputs (caller-owned)      */
+    size_t arena_bytes;
+    void *table_arena;       /* device memory for descriptor tables           */
+    size_t table_bytes;
+    int32_t max_inflight;    /* requests admitted but not yet complete (slots) */
+    int32_t n_streams;       /* 1..8 streams, default priority                */
+    int32_t max_batch;       /* requests per batched launch                    */
+    int32_t depth;           /* batches in flight per stream (1..4)           */
+    int32_t release_on_complete; /* 1: free an output as soon as it completes;
+                                  * 0: keep every output (results[i].out)    */
+} salt_server_config;
+
+typedef struct {
+    double arrival_s;                       /* seconds from the start of the run */
+    int32_t tree;                           /* catalogue index                   */
+    int32_t dtype;
+    int64_t n;
+    const void *operands[SALT_MAX_OPERANDS];  /* device pointers, as salt_eval   */
+    double scalars[SALT_MAX_SCALARS];
+} salt_request;
+
+typedef struct {
+    double arrival_s, admit_s, launch_s, complete_s;  /* seconds from the start */
+    void *out;            /* the output in the arena (valid only when kept)     */
+    int32_t status;       /* SALT_OK, or why the request was rejected          */
+    int32_t batch;        /* index of the batched launch that ran it           */
+} salt_request_result;
+
+/* Run `count` requests (sorted by arrival_s) through the server and fill
+ * results[0..count). Host memory for staging is allocated and freed inside
+ * the call (pinned); no device memory is allocated. Returns SALT_ERR_ARG on a
+ * bad configuration, SALT_ERR_DEVICE on a HIP failure; a bad request is
+ * rejected with its own status and does not stop the others. */
+salt_status salt_serve_trace(const salt_server_config *cfg, const salt_request *requests,
+                             int32_t count, salt_request_result *results);
+
 /* Validate a program without touching the GPU. On success fills
  * *stack_need (maximum stack depth) and *n_loads (distinct operands read)
  * when those pointers are non-null. */

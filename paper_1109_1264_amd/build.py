@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsalt.so")
 
-HIP_SOURCES = ["eval.hip", "reduce.hip", "batch.hip", "api.hip"]
+HIP_SOURCES = ["eval.hip", "reduce.hip", "batch.hip", "server.hip", "api.hip"]
 CXX_SOURCES = ["program.cpp"]
 ARCH = "gfx950"
 

@@ -23,6 +23,7 @@
 #include "launch.hpp"
 #include "program.hpp"
 #include "salt.h"
+#include "server.hpp"
 
 namespace salt {
 namespace {
@@ -337,6 +338,13 @@ salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, v
 }
 
 }  // namespace
+
+salt_status tuned_config(int kind, int route, int dtype, int64_t n, salt_launch_config *out) {
+    if (!out || !dtype_ok(dtype)) return SALT_ERR_ARG;
+    *out = lookup(kind, route, dtype, n, kind == kNrm2 ? 1 : kind == kBatch ? 4 : 2);
+    return SALT_OK;
+}
+
 }  // namespace salt
 
 extern "C" {
@@ -392,6 +400,14 @@ salt_status salt_nrm2(int64_t n, const void *x, void *result, void *workspace, s
 salt_status salt_nrm2_ex(int64_t n, const void *x, void *result, void *workspace, size_t ws_bytes,
                          salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
     return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, cfg, true);
+}
+
+salt_status salt_serve_trace(const salt_server_config *cfg, const salt_request *requests, int32_t count,
+                             salt_request_result *results) {
+    std::string why;
+    const salt_status s = serve_trace_impl(cfg, requests, count, results, &why);
+    if (s != SALT_OK) return fail(s, why);
+    return SALT_OK;
 }
 
 salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len, int32_t n_operands,

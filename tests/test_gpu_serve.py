@@ -1,0 +1,93 @@
+"""The serving loop: every served result equals the same request run alone
+(bit-exact), admission by memory works under tight budgets, requests that
+can never fit are rejected instead of hanging, and the recorded times are
+ordered."""
+from __future__ import annotations
+
+import pytest
+
+from paper_1109_1264_amd import salt as S
+from paper_1109_1264_amd import serve as V
+
+pytestmark = pytest.mark.gpu
+
+ES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+
+
+@pytest.fixture(scope="module")
+def pool():
+    return V.Pool(256 << 20, seed=5000)
+
+
+def alone_bytes(pool, m):
+    import torch
+
+    tree, dt, n, offs, alpha = m
+    prog = dict(S.salt_catalogue())[tree]
+    ops = [pool.buf[dt][o:o + n] for o in offs]
+    out = torch.empty(n, dtype=pool.buf[dt].dtype, device="cuda")
+    S.salt_eval(prog, ops, [alpha], out)
+    return out.view(torch.uint8)
+
+
+def served_bytes(arena, r, m):
+    off = r.out - arena.data_ptr()
+    return arena.view(__import__("torch").uint8)[off:off + m[2] * ES[m[1]]]
+
+
+def test_served_equals_alone(pool):
+    import torch
+
+    arena, table = V.default_buffers(arena_bytes=1 << 30, table_bytes=16 << 20)
+    trace, meta = V.make_trace(pool, 400, seed=5001, rate=20000.0, lo=8, hi=17)
+    res = V.serve(trace, arena, table, n_streams=3, max_batch=64, keep_outputs=True)
+    torch.cuda.synchronize()
+    batches = {r.batch for r in res}
+    assert len(batches) > 1                       # work was split into several launches
+    assert all(r.status == 0 for r in res)
+    for i, (r, m) in enumerate(zip(res, meta)):
+        got = served_bytes(arena, r, m)
+        want = alone_bytes(pool, m)
+        assert torch.equal(got, want), (i, m[:3])
+        assert r.arrival_s <= r.admit_s + 1e-9 and r.admit_s <= r.launch_s + 1e-9
+        assert r.complete_s >= r.launch_s - 5e-4      # GPU clock mapped to the host clock
+    s = V.summarize(res, meta)
+    assert s["requests"] == 400 and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_tiny_arena_admission(pool):
+    """An arena that holds only a few outputs: requests wait for memory,
+    all complete, and outputs are still right."""
+    import torch
+
+    arena, table = V.default_buffers(arena_bytes=1 << 20, table_bytes=4 << 20)
+    trace, meta = V.make_trace(pool, 120, seed=5002, rate=None, lo=8, hi=15, mix=(("f64", 1.0),))
+    res = V.serve(trace, arena, table, n_streams=2, max_batch=8, depth=1, max_inflight=4)
+    assert all(r.status == 0 for r in res)
+    assert len({r.batch for r in res}) >= 30      # at most 4 in flight at a time
+    # too big for the arena: rejected up front, the rest still run
+    trace, meta = V.make_trace(pool, 5, seed=5003, rate=None, lo=17, hi=18, mix=(("f64", 1.0),))
+    res = V.serve(trace, arena, table, n_streams=1, max_batch=8, depth=1)
+    assert all(r.status == S.ERR_UNSUPPORTED for r in res)
+
+
+def test_kept_outputs_exhaust_the_arena_without_hanging(pool):
+    arena, table = V.default_buffers(arena_bytes=1 << 20, table_bytes=4 << 20)
+    trace, meta = V.make_trace(pool, 40, seed=5004, rate=None, lo=14, hi=14, mix=(("f64", 1.0),))
+    # each output is 128 KiB: 8 fit, the rest cannot ever be admitted
+    res = V.serve(trace, arena, table, n_streams=2, max_batch=4, depth=1, keep_outputs=True)
+    st = [r.status for r in res]
+    assert st.count(0) == 8 and st.count(S.ERR_UNSUPPORTED) == 32
+
+
+def test_bad_config_is_rejected(pool):
+    import ctypes
+
+    arena, table = V.default_buffers(arena_bytes=1 << 20, table_bytes=4 << 20)
+    trace, _ = V.make_trace(pool, 3, seed=5005, rate=None, lo=8, hi=9)
+    L = V._declare()
+    res = (V.RequestResult * 3)()
+    cfg = V.ServerConfig(arena.data_ptr(), 1 << 20, table.data_ptr(), 4 << 20, 16, 9, 8, 1, 1)
+    assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # 9 streams
+    cfg = V.ServerConfig(arena.data_ptr(), 1 << 20, table.data_ptr(), 1 << 10, 16, 2, 8, 1, 1)
+    assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # table too small
