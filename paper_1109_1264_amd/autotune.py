@@ -32,7 +32,7 @@ def _torch_dtype(d):
 
 def candidates(kind: str, n: int, dtype: int, cus: int):
     unrolls = (1, 2, 4, 8) if kind == "eval" else (2, 4, 8, 16)
-    grids = [0] + [cus * k for k in (1, 2, 4, 8, 16)]
+    grids = [0] + [cus * k for k in ((1, 2, 4, 8) if kind == "batch" else (1, 2, 4, 8, 16))]
     out = []
     for u in unrolls:
         for nt in (0, 1):
@@ -120,6 +120,79 @@ def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbos
     return rows
 
 
+class BatchWorkload:
+    """A batched launch of one catalogue tree over items of the given lengths
+    (operands carved from flat device buffers at 64-element boundaries)."""
+
+    def __init__(self, tree: str, dtype: int, lengths, with_dot: bool, seed: int = 1):
+        import numpy as np
+        import torch
+
+        from .batch import Batch
+
+        td = _torch_dtype(dtype)
+        prog = dict(S.salt_catalogue())[tree]
+        self.route = [name for name, _ in S.salt_catalogue()].index(tree)
+        nops = 1 + max([t >> 8 for t in prog if t & 0xFF == S.LOAD], default=-1)
+        offs = np.zeros(len(lengths) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum((np.asarray(lengths) + 63) // 64 * 64)
+        cap = int(offs[-1])
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        self.bufs = [torch.rand(cap, device="cuda", generator=g).to(td) for _ in range(nops)]
+        self.out = torch.empty(cap, dtype=td, device="cuda")
+        self.dots = torch.empty(len(lengths), dtype=torch.float64 if dtype == S.F64 else torch.float32,
+                                device="cuda")
+        items = []
+        for k, n in enumerate(lengths):
+            a, b = int(offs[k]), int(offs[k]) + int(n)
+            items.append({"n": int(n), "operands": [t[a:b] for t in self.bufs], "scalars": [1.25],
+                          "out": self.out[a:b], "dot_out": self.dots[k:k + 1] if with_dot else None})
+        self.batch = Batch(prog, items, dtype)
+        self.total = int(np.sum(lengths))
+        self.arrays = nops + 1
+
+    def fn(self):
+        return lambda cfg: self.batch.launch(config=cfg)
+
+
+def tune_batch(tree: str, dtype: int, scenarios, with_dot: bool, reps: int = 10, verbose: bool = False):
+    """One row per scenario (a list of item lengths), keyed by log2 of the
+    total number of elements."""
+    import math
+
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rows = []
+    for lengths in scenarios:
+        w = BatchWorkload(tree, dtype, lengths, with_dot)
+        fn = w.fn()
+        best = None
+        for cfg in candidates("batch", w.total, dtype, cus):
+            t = time_config(fn, cfg, reps)
+            if best is None or t < best[0]:
+                best = (t, cfg)
+        t, (u, nt, b) = best
+        l = int(math.log2(max(1, w.total)))
+        gbps = w.arrays * w.total * S.ELEM_BYTES[dtype] / (t * 1e-3) / 1e9
+        rows.append(("batch", w.route, dtype, l, u, nt, b, t, gbps))
+        if verbose:
+            print("tuned batch %s %s %d items 2^%d elems: unroll=%d nt=%d blocks=%d %.4f ms %.0f GB/s"
+                  % (tree, S.DTYPE_NAMES[dtype], len(lengths), l, u, nt, b, t, gbps), file=sys.stderr, flush=True)
+        del w
+        torch.cuda.empty_cache()
+    return rows
+
+
+def serving_scenarios(seed: int = 11):
+    """Item-length mixes like the served batches: log-uniform 2^8..2^24."""
+    import numpy as np
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [np.rint(2.0 ** rng.uniform(8, 24, k)).astype(np.int64) for k in (4, 16, 64, 256)]
+
+
 def write_table(rows, path: str) -> None:
     with open(path, "w") as fh:
         fh.write("# libsalt tuning table, written by paper_1109_1264_amd.autotune\n")
@@ -135,18 +208,35 @@ def main(argv=None) -> int:
     ap.add_argument("--dtypes", default="f64,f32,bf16,f16")
     ap.add_argument("--log2n", default="10-28")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--step", type=int, default=2, help="tune every step-th log2 size")
+    ap.add_argument("--kinds", default="eval,dot,nrm2,batch")
     ap.add_argument("--json", default=None, help="also write all rows as JSON here")
     args = ap.parse_args(argv)
     lo, hi = (int(v) for v in args.log2n.split("-"))
+    sizes = list(range(lo, hi + 1, args.step))
+    if sizes[-1] != hi:
+        sizes.append(hi)
+    kinds = args.kinds.split(",")
     t0 = time.time()
     rows = []
     for dname in args.dtypes.split(","):
         d = DT_NAMES[dname]
-        # keep the largest size within memory: 2^28 elements of any type fit
         for kind in ("dot", "nrm2"):
-            rows += tune(kind, None, d, range(lo, hi + 1), args.reps, verbose=True)
-        for tree in args.trees.split(","):
-            rows += tune("eval", tree, d, range(lo, hi + 1), args.reps, verbose=True)
+            if kind in kinds:
+                rows += tune(kind, None, d, sizes, args.reps, verbose=True)
+        if "eval" in kinds:
+            for tree in args.trees.split(","):
+                rows += tune("eval", tree, d, sizes, args.reps, verbose=True)
+    if "batch" in kinds:
+        from . import workloads
+
+        c4 = [workloads.batch_lengths(4096, seed=workloads.SEED_BATCHED),
+              workloads.batch_lengths(512, seed=workloads.SEED_BATCHED + 1)]
+        rows += tune_batch("abc", S.F32, c4, with_dot=True, reps=args.reps, verbose=True)
+        for dname in ("f32", "bf16", "f64"):
+            for tree in ("fig1", "axpy", "tree5", "t4", "t5"):
+                rows += tune_batch(tree, DT_NAMES[dname], serving_scenarios(), with_dot=False,
+                                   reps=args.reps, verbose=True)
     write_table(rows, args.out)
     if args.json:
         with open(args.json, "w") as fh:

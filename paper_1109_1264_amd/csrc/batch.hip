@@ -11,7 +11,8 @@
 // operand 1) from the same registers: the operands are read once for both.
 // The dot's accumulation order inside a tile and the combine over the item's
 // tiles are exactly those of salt_dot, so an item's dot has the same bits in
-// a batch as alone. A second small kernel combines each item's partials.
+// a batch as alone. A second small kernel combines each item's partials, one
+// wave per item.
 #include "batch.hpp"
 #include "device.hpp"
 #include "expr.hpp"
@@ -105,16 +106,17 @@ __global__ __launch_bounds__(kBlock) void k_batch(const DevItem *__restrict__ it
     }
 }
 
+// One wave per item: the combine of salt_dot's pass 2, wave-serialised.
 template <int DT>
-__global__ __launch_bounds__(kFinalBlock) void k_batch_combine(const DevItem *__restrict__ items, int count,
-                                                               const double *ws) {
-    __shared__ double lds[kFinalBlock / 64];
+__global__ __launch_bounds__(kBlock) void k_batch_combine(const DevItem *__restrict__ items, int count,
+                                                          const double *ws) {
     constexpr int64_t T = tile_elems<DT>();
-    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+    constexpr int kWaves = kBlock / 64;
+    for (int k = blockIdx.x * kWaves + (threadIdx.x >> 6); k < count; k += gridDim.x * kWaves) {
         const DevItem &it = items[k];
         if (!it.dot_out) continue;
-        const double r = combine_partials(ws + it.tile_begin, (it.n + T - 1) / T, lds);
-        if (threadIdx.x == 0) store_result<DT, false>(it.dot_out, r);
+        const double r = combine_partials_wave(ws + it.tile_begin, (it.n + T - 1) / T);
+        if ((threadIdx.x & 63) == 0) store_result<DT, false>(it.dot_out, r);
     }
 }
 
@@ -127,8 +129,9 @@ static int launch_batch_u(const BatchLaunch &L) {
                            (hipStream_t)L.stream, L.items, L.tile_item, L.total_tiles, L.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !DOT || L.count == 0) return (int)e;
-    const int cgrid = L.count < 8192 ? L.count : 8192;
-    hipLaunchKernelGGL((k_batch_combine<DT>), dim3(cgrid), dim3(kFinalBlock), 0, (hipStream_t)L.stream,
+    const int waves = kBlock / 64;
+    const int cgrid = (L.count + waves - 1) / waves < 4096 ? (L.count + waves - 1) / waves : 4096;
+    hipLaunchKernelGGL((k_batch_combine<DT>), dim3(cgrid), dim3(kBlock), 0, (hipStream_t)L.stream,
                        L.items, L.count, (const double *)L.ws);
     return (int)hipGetLastError();
 }

@@ -138,6 +138,27 @@ __device__ __forceinline__ double combine_partials(const double *part, int64_t c
     return block_sum<kFinalBlock / 64>(v, lds);
 }
 
+// The same arithmetic as combine_partials, done by a single wave: it visits
+// the 16 waves of the 1024-lane combine one after another (lane j of virtual
+// wave w plays lane 64*w + j), so the result has the same bits. Used where
+// one workgroup per reduction would be wasteful (many small reductions).
+__device__ __forceinline__ double combine_partials_wave(const double *part, int64_t count) {
+    constexpr int W = kFinalBlock / 64;
+    const int lane = threadIdx.x & 63;
+    double w[W];
+#pragma unroll
+    for (int vw = 0; vw < W; ++vw) {
+        double v = 0.0;
+        for (int64_t i = vw * 64 + lane; i < count; i += kFinalBlock) v = v + part[i];
+        w[vw] = wave_sum(v);
+    }
+#pragma unroll
+    for (int h = W / 2; h >= 1; h >>= 1)
+#pragma unroll
+        for (int k = 0; k < h; ++k) w[k] = w[2 * k] + w[2 * k + 1];
+    return w[0];
+}
+
 template <int DT, bool NRM>
 __device__ __forceinline__ void store_result(void *result, double r) {
     if constexpr (NRM) r = __builtin_sqrt(r);

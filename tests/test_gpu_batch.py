@@ -141,3 +141,25 @@ def test_c4_shape_small():
     b = Batch(ABC, items, CODE[dtype])
     b.graph().launch()
     check(items, host, dtype, alone_dot=False)
+
+
+def test_item_with_more_partials_than_combine_lanes():
+    """An item with more than 1024 tiles: the one-wave combine of the batched
+    path and the 1024-lane pass 2 of salt_dot must still agree bit for bit."""
+    import torch
+
+    dtype = "bf16"
+    Tt = S.salt_reduce_tile_elems(CODE[dtype])
+    lengths = [1030 * Tt + 17, 5, Tt * 3]
+    items = []
+    for i, n in enumerate(lengths):
+        a, b, c = workloads.uniform_device(n, dtype, 77 + i, 3)
+        items.append({"n": n, "operands": [a, b, c], "scalars": [0.75], "out": None,
+                      "dot_out": torch.empty(1, dtype=torch.float32, device="cuda")})
+    bt = Batch(ABC, items, CODE[dtype])
+    bt.launch()
+    torch.cuda.synchronize()
+    for it in items:
+        r = S.salt_dot(it["operands"][0], it["operands"][1])
+        torch.cuda.synchronize()
+        assert float(r.item()) == float(it["dot_out"].item()), it["n"]
