@@ -11,8 +11,11 @@ once: 96 B per element) / wall time per step, in GB/s. Per-kernel durations
 are HIP events recorded on the launch stream around every launch inside the
 timed region.
 
-The same JSON line also reports the three systems layers beside the plain
-binary64 kernels (each measured after the timed step):
+The same JSON line also reports the whole size sweep and the three systems
+layers beside the plain binary64 kernels (each measured after the timed
+step):
+    sweep:     axpy, dot, nrm2 and the 5-operand tree for n = 2^10 .. 2^28 in
+               binary64 and binary32 (device time per launch, GB/s);
     precision: dot / nrm2 at n = 2^26, storage FP64 / FP32 / BF16, with the
                error against the binary64 oracle per result;
     batched:   4096 lognormal-length instances of alpha*a + (b - c) plus
@@ -22,7 +25,7 @@ binary64 kernels (each measured after the timed step):
                saturation rate, p50 / p99 latency and throughput.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
-                    [--sections main,precision,batched,served]
+                    [--sections main,sweep,precision,batched,served]
 """
 from __future__ import annotations
 
@@ -244,6 +247,75 @@ def main_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5):
 
 
 # ---------------------------------------------------------------------------
+# size sweep (BLAS-1 sweep, every size)
+# ---------------------------------------------------------------------------
+
+def graph_ms(fn, reps: int) -> float:
+    """Per-launch time of fn() from a captured graph of `reps` launches,
+    replayed between two events: device time of back-to-back launches, free
+    of Python launch overhead."""
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) / reps
+    del g
+    return t
+
+
+def section_sweep(args):
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    T = salt.token
+    tree5 = [T(salt.LOAD, 0), T(salt.LOAD, 1), T(salt.MUL), T(salt.LOAD, 2), T(salt.LOAD, 3), T(salt.MUL),
+             T(salt.ADD), T(salt.LOAD, 4), T(salt.SUB)]
+    out = {"timing": "per-launch device time from a replayed graph of back-to-back launches",
+           "regime": "sizes whose working set is >= 1 GiB are HBM-bound; smaller ones run from the "
+                     "256 MiB last-level cache, L2 or are launch-bound"}
+    hi = args.log2n
+    for name in ("f64", "f32"):
+        code = salt.F64 if name == "f64" else salt.F32
+        es = 8 if name == "f64" else 4
+        log("bench: sweep %s 2^10..2^%d" % (name, hi))
+        a, b, c, e, f = workloads.uniform_device(1 << hi, name, workloads.sweep_seed(1 << hi), 5)
+        d = torch.empty(1 << hi, dtype=a.dtype, device="cuda")
+        ws = salt.workspace(1 << hi, code)
+        r = torch.empty(1, dtype=torch.float64 if name == "f64" else torch.float32, device="cuda")
+        rows = {"axpy": [], "dot": [], "nrm2": [], "tree5": []}
+        for l in range(10, hi + 1):
+            n = 1 << l
+            al = workloads.alpha(workloads.sweep_seed(n))
+            v = [t[:n] for t in (a, b, c, e, f)]
+            dn = d[:n]
+            fns = {"axpy": (lambda: salt.salt_axpy(al, v[0], dn), 3),
+                   "dot": (lambda: salt.salt_dot(v[0], v[1], result=r, ws=ws), 2),
+                   "nrm2": (lambda: salt.salt_nrm2(v[2], result=r, ws=ws), 1),
+                   "tree5": (lambda: salt.salt_eval(tree5, v, [], dn), 6)}
+            reps = 50 if l <= 20 else (10 if l <= 24 else 4)
+            for k, (fn, arrays) in fns.items():
+                t = graph_ms(fn, reps)
+                rows[k].append([l, round(t, 5), round(arrays * es * n / (t * 1e-3) / 1e9, 1)])
+        out[name] = {k: {"columns": ["log2n", "ms", "GBps"], "rows": v} for k, v in rows.items()}
+        del a, b, c, e, f, d, ws
+        torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # precision layer
 # ---------------------------------------------------------------------------
 
@@ -415,7 +487,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--sections", default="main,precision,batched,served")
+    ap.add_argument("--sections", default="main,sweep,precision,batched,served")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-log2n", type=int, default=26)
@@ -443,6 +515,8 @@ def main() -> int:
         return 0
     if "main" in sections:
         section_main(args, out)
+    if "sweep" in sections:
+        out["sweep"] = section_sweep(args)
     if "precision" in sections:
         out["precision"] = section_precision(args)
     if "batched" in sections:
