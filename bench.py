@@ -16,6 +16,9 @@ layers beside the plain binary64 kernels (each measured after the timed
 step):
     sweep:     axpy, dot, nrm2 and the 5-operand tree for n = 2^10 .. 2^28 in
                binary64 and binary32 (device time per launch, GB/s);
+    fusion:    one fused pass against the same result composed from
+               single-operation calls (out-of-place scale, a + (b - c),
+               dot of two trees), with identical bits;
     precision: dot / nrm2 at n = 2^26, storage FP64 / FP32 / BF16, with the
                error against the binary64 oracle per result;
     batched:   4096 lognormal-length instances of alpha*a + (b - c) plus
@@ -25,7 +28,7 @@ step):
                saturation rate, p50 / p99 latency and throughput.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
-                    [--sections main,sweep,precision,batched,served]
+                    [--sections main,sweep,fusion,precision,batched,served]
 """
 from __future__ import annotations
 
@@ -316,6 +319,69 @@ def section_sweep(args):
 
 
 # ---------------------------------------------------------------------------
+# fusion against composition of single-operation calls
+# ---------------------------------------------------------------------------
+
+def section_fusion(args):
+    """The paper's out-of-place scale experiment (Sec. 5, Fig. 6: BLAS needs a
+    copy and a scal) and two more trees, fused into one pass against the same
+    results composed from single-operation kernels; results are checked for
+    identical bits."""
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    n = 1 << args.log2n
+    log("bench: fusion vs composition, n = 2^%d" % args.log2n)
+    T = salt.token
+    L0, L1, L2 = T(salt.LOAD, 0), T(salt.LOAD, 1), T(salt.LOAD, 2)
+    a, b, c, e = workloads.uniform_device(n, "f64", workloads.sweep_seed(n) + 1, 4)
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    t = torch.empty(n, dtype=torch.float64, device="cuda")
+    ws = salt.workspace(n, salt.F64)
+    r1 = torch.empty(1, dtype=torch.float64, device="cuda")
+    r2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    al = workloads.alpha(7)
+    scale = [T(salt.SCALAR, 0), L0, T(salt.MUL)]
+    cases = {
+        "scale_out_of_place": {
+            "fused": (lambda: salt.salt_eval(scale, [a], [al], d), 16),
+            "composed": (lambda: (salt.salt_eval([L0], [a], [], t), salt.salt_eval(scale, [t], [al], t)), 32),
+            "what": "d = alpha*a: one pass vs copy then in-place scale"},
+        "fig1": {
+            "fused": (lambda: salt.salt_eval([L0, L1, L2, T(salt.SUB), T(salt.ADD)], [a, b, c], [], d), 32),
+            "composed": (lambda: (salt.salt_eval([L0, L1, T(salt.SUB)], [b, c], [], t),
+                                  salt.salt_eval([L0, L1, T(salt.ADD)], [a, t], [], t)), 48),
+            "what": "d = a + (b - c): one pass vs t = b - c, d = a + t"},
+        "dot_of_trees": {
+            "fused": (lambda: salt.salt_dot_expr([L0, L1, T(salt.ADD)], [L0, L1, T(salt.SUB)], [c, e], [],
+                                                 result=r1, ws=ws), 16),
+            "composed": (lambda: (salt.salt_eval([L0, L1, T(salt.ADD)], [c, e], [], d),
+                                  salt.salt_eval([L0, L1, T(salt.SUB)], [c, e], [], t),
+                                  salt.salt_dot(d, t, result=r2, ws=ws)), 48),
+            "what": "dot(c + e, c - e): one pass vs two evaluations and a dot"},
+    }
+    out = {"n": n, "dtype": "f64"}
+    for name, cs in cases.items():
+        tf = event_ms(cs["fused"][0], 10)
+        fused_bits = (d.clone() if name != "dot_of_trees" else r1.clone())
+        tc = event_ms(cs["composed"][0], 10)
+        comp_bits = (t if name != "dot_of_trees" else r2)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(fused_bits.view(torch.int64), comp_bits.view(torch.int64)))
+        out[name] = {"what": cs["what"], "fused_ms": round(tf, 4), "composed_ms": round(tc, 4),
+                     "speedup": round(tc / tf, 3), "fused_bytes_per_elem": cs["fused"][1],
+                     "composed_bytes_per_elem": cs["composed"][1],
+                     "fused_GBps": round(cs["fused"][1] * n / (tf * 1e-3) / 1e9, 1),
+                     "composed_GBps": round(cs["composed"][1] * n / (tc * 1e-3) / 1e9, 1),
+                     "same_bits": same}
+    del a, b, c, e, d, t, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # precision layer
 # ---------------------------------------------------------------------------
 
@@ -487,7 +553,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--sections", default="main,sweep,precision,batched,served")
+    ap.add_argument("--sections", default="main,sweep,fusion,precision,batched,served")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-log2n", type=int, default=26)
@@ -517,6 +583,8 @@ def main() -> int:
         section_main(args, out)
     if "sweep" in sections:
         out["sweep"] = section_sweep(args)
+    if "fusion" in sections:
+        out["fusion"] = section_fusion(args)
     if "precision" in sections:
         out["precision"] = section_precision(args)
     if "batched" in sections:

@@ -119,6 +119,30 @@ salt_status salt_dot(int64_t n, const void *x, const void *y, void *result,
 salt_status salt_nrm2(int64_t n, const void *x, void *result,
                       void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream);
 
+/* Lazy evaluation inside a reduction (Sec. 2: trees are evaluated where they
+ * are needed, e.g. in a dot product or a norm): dot(P, Q) = sum_i P_i * Q_i
+ * for two postfix programs P and Q over one operand list, and
+ * nrm2(P) = sqrt(sum_i P_i^2), in one pass that reads each operand used by
+ * either program once and writes no vector. The elements P_i and Q_i are the
+ * values salt_eval would produce, and they are summed in salt_dot's order, so
+ * the result has the same bits as salt_dot applied to the vectors salt_eval
+ * would write (the product of two values is symmetric, so the order of P
+ * and Q does not matter). Programs, operands and scalars are validated as
+ * for salt_eval (operands need not all be used); workspace and result as for
+ * salt_dot. One of P and Q must fit in SALT_MAX_STACK - 1 stack slots (it
+ * runs on top of the other's result), else SALT_ERR_UNSUPPORTED. */
+salt_status salt_dot_expr(const uint32_t *prog_x, int32_t len_x,
+                          const uint32_t *prog_y, int32_t len_y,
+                          const void *const *operands, int32_t n_operands,
+                          const double *scalars, int32_t n_scalars, int64_t n,
+                          void *result, void *workspace, size_t ws_bytes,
+                          salt_dtype dtype, void *hip_stream);
+salt_status salt_nrm2_expr(const uint32_t *prog, int32_t prog_len,
+                           const void *const *operands, int32_t n_operands,
+                           const double *scalars, int32_t n_scalars, int64_t n,
+                           void *result, void *workspace, size_t ws_bytes,
+                           salt_dtype dtype, void *hip_stream);
+
 /* ---- launch control (autotuning and introspection) ------------------------
  * The paper picks the number of instruction packages per loop by trial
  * (Sec. 4.3); here the equivalent knobs are chosen per tree, element type
@@ -126,7 +150,8 @@ salt_status salt_nrm2(int64_t n, const void *x, void *result,
  * None of them changes any result bit. */
 typedef struct {
     int32_t unroll;      /* 16-byte chunks per operand per lane per burst:
-                          * eval 1, 2, 4, 8; dot/nrm2 2, 4, 8, 16; 0 = tuned */
+                          * eval 1, 2, 4, 8; dot/nrm2 2, 4, 8, 16; batched
+                          * 2, 4, 8; 0 = tuned */
     int32_t nontemporal; /* 1 streaming loads/stores, 0 normal, -1 = tuned */
     int64_t blocks;      /* workgroups: 0 = one per tile, >0 = grid-stride
                           * grid of that size, -1 = tuned */
@@ -138,6 +163,20 @@ salt_status salt_eval_ex(const uint32_t *prog, int32_t prog_len,
                          const double *scalars, int32_t n_scalars,
                          void *out, int64_t n, salt_dtype dtype, void *hip_stream,
                          const salt_launch_config *cfg);
+
+/* salt_dot_expr / salt_nrm2_expr with explicit launch knobs (cfg NULL =
+ * tuned; unroll 2, 4 or 8 chunks per interpreter run, 16 runs as 8). */
+salt_status salt_dot_expr_ex(const uint32_t *prog_x, int32_t len_x,
+                             const uint32_t *prog_y, int32_t len_y,
+                             const void *const *operands, int32_t n_operands,
+                             const double *scalars, int32_t n_scalars, int64_t n,
+                             void *result, void *workspace, size_t ws_bytes,
+                             salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg);
+salt_status salt_nrm2_expr_ex(const uint32_t *prog, int32_t prog_len,
+                              const void *const *operands, int32_t n_operands,
+                              const double *scalars, int32_t n_scalars, int64_t n,
+                              void *result, void *workspace, size_t ws_bytes,
+                              salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg);
 
 /* salt_dot / salt_nrm2 with explicit launch knobs (cfg NULL = tuned). */
 salt_status salt_dot_ex(int64_t n, const void *x, const void *y, void *result,

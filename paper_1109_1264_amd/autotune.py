@@ -31,7 +31,8 @@ def _torch_dtype(d):
 
 
 def candidates(kind: str, n: int, dtype: int, cus: int):
-    unrolls = (1, 2, 4, 8) if kind == "eval" else (2, 4, 8, 16)
+    unrolls = {"eval": (1, 2, 4, 8), "interp": (1, 2, 4), "batch": (2, 4, 8), "dotx": (2, 4, 8),
+               "nrm2x": (2, 4, 8)}.get(kind, (2, 4, 8, 16))
     grids = [0] + [cus * k for k in ((1, 2, 4, 8) if kind == "batch" else (1, 2, 4, 8, 16))]
     out = []
     for u in unrolls:
@@ -57,6 +58,14 @@ def time_config(fn, cfg, reps: int, warm: int = 2) -> float:
     return ts[len(ts) // 2]
 
 
+# Representative programs outside the catalogue: they run on the interpreter
+# (eval, route -1) and on the expression reductions (dot / nrm2, route -2).
+T_ = S.token
+INTERP_PROG = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD), T_(S.LOAD, 2), T_(S.MUL)]   # (a + b) * c
+EXPR_P = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD)]                                  # a + b
+EXPR_Q = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.SUB)]                                  # a - b
+
+
 class Workload:
     """Device buffers for one (kind, tree, dtype) at the largest size swept."""
 
@@ -67,7 +76,19 @@ class Workload:
         td = _torch_dtype(dtype)
         cat = dict(S.salt_catalogue())
         self.route = -1
-        if kind == "eval":
+        if kind == "interp":
+            self.prog = INTERP_PROG
+            self.ops = [torch.rand(n_max, device="cuda").to(td) for _ in range(3)]
+            self.sc = []
+            self.out = torch.empty(n_max, dtype=td, device="cuda")
+            self.arrays = 4
+        elif kind in ("dotx", "nrm2x"):
+            self.route = -2
+            self.ops = [torch.rand(n_max, device="cuda").to(td) for _ in range(2)]
+            self.ws = S.workspace(n_max, dtype)
+            self.res = torch.empty(1, dtype=torch.float64 if dtype == S.F64 else torch.float32, device="cuda")
+            self.arrays = 2
+        elif kind == "eval":
             self.prog = cat[tree]
             self.route = [name for name, _ in S.salt_catalogue()].index(tree)
             nops = 1 + max([t >> 8 for t in self.prog if t & 0xFF == S.LOAD], default=-1)
@@ -84,7 +105,14 @@ class Workload:
             self.arrays = 2 if kind == "dot" else 1
 
     def fn(self, n: int):
-        if self.kind == "eval":
+        if self.kind == "dotx":
+            ops = [o[:n] for o in self.ops]
+            return lambda cfg: S.salt_dot_expr(EXPR_P, EXPR_Q, ops, [], n=n, result=self.res, ws=self.ws,
+                                               config=cfg)
+        if self.kind == "nrm2x":
+            ops = [o[:n] for o in self.ops]
+            return lambda cfg: S.salt_nrm2_expr(EXPR_P, ops, [], n=n, result=self.res, ws=self.ws, config=cfg)
+        if self.kind in ("eval", "interp"):
             ops = [o[:n] for o in self.ops]
             out = self.out[:n]
             return lambda cfg: S.salt_eval(self.prog, ops, self.sc, out, config=cfg)
@@ -113,7 +141,8 @@ def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbos
                 best = (t, cfg)
         t, (u, nt, b) = best
         gbps = w.arrays * n * S.ELEM_BYTES[dtype] / (t * 1e-3) / 1e9
-        rows.append((kind, w.route, dtype, l, u, nt, b, t, gbps))
+        table_kind = {"interp": "eval", "dotx": "dot", "nrm2x": "nrm2"}.get(kind, kind)
+        rows.append((table_kind, w.route, dtype, l, u, nt, b, t, gbps))
         if verbose:
             print("tuned %s %s %s 2^%d: unroll=%d nt=%d blocks=%d %.4f ms %.0f GB/s"
                   % (kind, tree or "", S.DTYPE_NAMES[dtype], l, u, nt, b, t, gbps), file=sys.stderr, flush=True)
@@ -209,7 +238,7 @@ def main(argv=None) -> int:
     ap.add_argument("--log2n", default="10-28")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--step", type=int, default=2, help="tune every step-th log2 size")
-    ap.add_argument("--kinds", default="eval,dot,nrm2,batch")
+    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,dotx,nrm2x,batch")
     ap.add_argument("--json", default=None, help="also write all rows as JSON here")
     args = ap.parse_args(argv)
     lo, hi = (int(v) for v in args.log2n.split("-"))
@@ -227,6 +256,9 @@ def main(argv=None) -> int:
         if "eval" in kinds:
             for tree in args.trees.split(","):
                 rows += tune("eval", tree, d, sizes, args.reps, verbose=True)
+        for kind in ("interp", "dotx", "nrm2x"):
+            if kind in kinds:
+                rows += tune(kind, None, d, sizes, args.reps, verbose=True)
     if "batch" in kinds:
         from . import workloads
 

@@ -21,7 +21,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsalt.so")
 
-HIP_SOURCES = ["eval.hip", "reduce.hip", "batch.hip", "server.hip", "api.hip"]
+HIP_SOURCES = ["batch_f64.hip", "batch_f32.hip", "batch_bf16.hip", "batch_f16.hip",
+               "reduce_f64.hip", "reduce_f32.hip", "reduce_bf16.hip", "reduce_f16.hip",
+               "eval.hip", "reduce.hip", "batch.hip", "server.hip", "api.hip"]
 CXX_SOURCES = ["program.cpp"]
 ARCH = "gfx950"
 
@@ -59,7 +61,7 @@ def build(verbose: bool = False) -> str:
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")
         jobs.append((["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
-    workers = min(len(jobs), max(1, min(8, os.cpu_count() or 1)))
+    workers = min(len(jobs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(workers) as ex:
         for p in ex.map(lambda j: _run(j[0]), jobs):
             if verbose and p.stderr:

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -178,7 +179,9 @@ salt_launch_config lookup(int kind, int route, int dtype, int64_t n, int n_array
     return best ? best->cfg : default_cfg(kind, dtype, n, n_arrays);
 }
 
-salt_status resolve(const salt_launch_config *req, salt_launch_config tuned, bool eval,
+// Knobs of a call: the tuned values, overridden by the caller's. Unroll
+// values: eval 1, 2, 4, 8; dot / nrm2 2, 4, 8, 16; batched 2, 4, 8.
+salt_status resolve(const salt_launch_config *req, salt_launch_config tuned, int kind,
                     salt_launch_config *out) {
     salt_launch_config c = tuned;
     if (req) {
@@ -189,7 +192,9 @@ salt_status resolve(const salt_launch_config *req, salt_launch_config tuned, boo
             return fail(SALT_ERR_ARG, "launch config out of range");
     }
     const int u = c.unroll;
-    const bool ok = eval ? (u == 1 || u == 2 || u == 4 || u == 8) : (u == 2 || u == 4 || u == 8 || u == 16);
+    const bool ok = kind == kEval ? (u == 1 || u == 2 || u == 4 || u == 8)
+                  : kind == kBatch ? (u == 2 || u == 4 || u == 8)
+                  : (u == 2 || u == 4 || u == 8 || u == 16);
     if (!ok) return fail(SALT_ERR_ARG, "unroll " + std::to_string(u) + " not available");
     *out = c;
     return SALT_OK;
@@ -214,7 +219,7 @@ salt_status eval_impl(const uint32_t *prog, int32_t prog_len, const void *const 
     if (p.n_scal > 0 && !scalars) return fail(SALT_ERR_ARG, "scalar array is NULL");
     const int route = route_of(p);
     salt_launch_config c;
-    s = resolve(cfg, lookup(kEval, route, dtype, n, p.n_loads + 1), true, &c);
+    s = resolve(cfg, lookup(kEval, route, dtype, n, p.n_loads + 1), kEval, &c);
     if (s != SALT_OK) return s;
     if (n == 0) return SALT_OK;
     if (!out) return fail(SALT_ERR_ARG, "output pointer is NULL");
@@ -267,7 +272,7 @@ salt_status reduce_impl(int64_t n, const void *x, const void *y, void *result, v
             return fail(SALT_ERR_WORKSPACE, "workspace overlaps an input");
     }
     salt_launch_config c;
-    salt_status s = resolve(cfg, lookup(nrm2 ? kNrm2 : kDot, -1, dtype, n, nrm2 ? 1 : 2), false, &c);
+    salt_status s = resolve(cfg, lookup(nrm2 ? kNrm2 : kDot, -1, dtype, n, nrm2 ? 1 : 2), nrm2 ? kNrm2 : kDot, &c);
     if (s != SALT_OK) return s;
     ReduceLaunch L;
     L.x = x;
@@ -318,7 +323,7 @@ salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, v
         if (ws_bytes < plan->ws_bytes) return fail(SALT_ERR_WORKSPACE, "workspace too small");
     }
     salt_launch_config c;
-    salt_status s = resolve(cfg, lookup(kBatch, plan->route, plan->dtype, plan->total_elems, 4), false, &c);
+    salt_status s = resolve(cfg, lookup(kBatch, plan->route, plan->dtype, plan->total_elems, 4), kBatch, &c);
     if (s != SALT_OK) return s;
     if (plan->count == 0) return SALT_OK;
     BatchFn fn = catalogue_batch_launcher(plan->route, plan->dtype);
@@ -335,6 +340,66 @@ salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, v
     L.blocks = c.blocks;
     L.stream = stream;
     return device_status((hipError_t)fn(L));
+}
+
+salt_status reduce_expr_impl(const uint32_t *px, int32_t lx, const uint32_t *py, int32_t ly,
+                             const void *const *operands, int32_t n_operands, const double *scalars,
+                             int32_t n_scalars, int64_t n, void *result, void *ws, size_t ws_bytes, int dtype,
+                             void *stream, bool nrm2, const salt_launch_config *cfg) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    if ((uint64_t)n > (uint64_t)INT64_MAX / 16) return fail(SALT_ERR_ARG, "length too large");
+    Program gx, gy;
+    std::string why;
+    salt_status s = compile_program(px, lx, n_operands, n_scalars, &gx, &why);
+    if (s != SALT_OK) return fail(s, "first program: " + why);
+    if (!nrm2) {
+        s = compile_program(py, ly, n_operands, n_scalars, &gy, &why);
+        if (s != SALT_OK) return fail(s, "second program: " + why);
+    }
+    // The second program runs one stack slot up, on the first one's result.
+    if (!nrm2 && gy.stack_need > SALT_MAX_STACK - 1) {
+        if (gx.stack_need <= SALT_MAX_STACK - 1) std::swap(gx, gy);  // the product is symmetric
+        else return fail(SALT_ERR_UNSUPPORTED, "both programs need all 8 stack slots");
+    }
+    const uint32_t mask = gx.load_mask | (nrm2 ? 0u : gy.load_mask);
+    if (mask && !operands) return fail(SALT_ERR_ARG, "operand array is NULL");
+    if ((gx.n_scal || (!nrm2 && gy.n_scal)) && !scalars) return fail(SALT_ERR_ARG, "scalar array is NULL");
+    if (!result) return fail(SALT_ERR_ARG, "result pointer is NULL");
+    ReduceExprLaunch L;
+    std::memset(&L, 0, sizeof L);
+    const size_t bytes = (size_t)n * esize(dtype);
+    const size_t need = salt_reduce_workspace_bytes(n, (salt_dtype)dtype);
+    bool vec = true;
+    for (int k = 0; k < SALT_MAX_OPERANDS; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        if (n > 0 && !operands[k]) return fail(SALT_ERR_ARG, "operand " + std::to_string(k) + " is NULL");
+        if (need > 0 && any_overlap(ws, need, operands[k], bytes))
+            return fail(SALT_ERR_WORKSPACE, "workspace overlaps an operand");
+        L.ops[k] = operands[k];
+        vec = vec && aligned16(operands[k]);
+    }
+    if (need > 0) {
+        if (!ws) return fail(SALT_ERR_WORKSPACE, "workspace is NULL");
+        if (((uintptr_t)ws & 7u) != 0) return fail(SALT_ERR_WORKSPACE, "workspace not 8-byte aligned");
+        if (ws_bytes < need) return fail(SALT_ERR_WORKSPACE, "workspace too small");
+    }
+    for (int j = 0; j < n_scalars && j < SALT_MAX_SCALARS; ++j) L.sc[j] = scalars ? scalars[j] : 0.0;
+    // Tuned knobs of the expression reductions live under route -2.
+    salt_launch_config c;
+    s = resolve(cfg, lookup(nrm2 ? kNrm2 : kDot, -2, dtype, n, nrm2 ? 1 : 2), nrm2 ? kNrm2 : kDot, &c);
+    if (s != SALT_OK) return s;
+    L.result = result;
+    L.unroll = c.unroll;
+    L.ws = (double *)ws;
+    L.n = n;
+    L.vec = vec ? 1 : 0;
+    L.mask = mask;
+    L.nontemporal = c.nontemporal;
+    L.blocks = c.blocks;
+    L.nrm2 = nrm2 ? 1 : 0;
+    L.stream = stream;
+    return device_status(launch_reduce_expr(L, gx, nrm2 ? nullptr : &gy, dtype));
 }
 
 }  // namespace
@@ -400,6 +465,37 @@ salt_status salt_nrm2(int64_t n, const void *x, void *result, void *workspace, s
 salt_status salt_nrm2_ex(int64_t n, const void *x, void *result, void *workspace, size_t ws_bytes,
                          salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
     return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, cfg, true);
+}
+
+salt_status salt_dot_expr(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,
+                          const void *const *operands, int32_t n_operands, const double *scalars,
+                          int32_t n_scalars, int64_t n, void *result, void *workspace, size_t ws_bytes,
+                          salt_dtype dtype, void *hip_stream) {
+    return reduce_expr_impl(prog_x, len_x, prog_y, len_y, operands, n_operands, scalars, n_scalars, n, result,
+                            workspace, ws_bytes, dtype, hip_stream, false, nullptr);
+}
+
+salt_status salt_dot_expr_ex(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,
+                             const void *const *operands, int32_t n_operands, const double *scalars,
+                             int32_t n_scalars, int64_t n, void *result, void *workspace, size_t ws_bytes,
+                             salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
+    return reduce_expr_impl(prog_x, len_x, prog_y, len_y, operands, n_operands, scalars, n_scalars, n, result,
+                            workspace, ws_bytes, dtype, hip_stream, false, cfg);
+}
+
+salt_status salt_nrm2_expr(const uint32_t *prog, int32_t prog_len, const void *const *operands,
+                           int32_t n_operands, const double *scalars, int32_t n_scalars, int64_t n, void *result,
+                           void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream) {
+    return reduce_expr_impl(prog, prog_len, nullptr, 0, operands, n_operands, scalars, n_scalars, n, result,
+                            workspace, ws_bytes, dtype, hip_stream, true, nullptr);
+}
+
+salt_status salt_nrm2_expr_ex(const uint32_t *prog, int32_t prog_len, const void *const *operands,
+                              int32_t n_operands, const double *scalars, int32_t n_scalars, int64_t n,
+                              void *result, void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream,
+                              const salt_launch_config *cfg) {
+    return reduce_expr_impl(prog, prog_len, nullptr, 0, operands, n_operands, scalars, n_scalars, n, result,
+                            workspace, ws_bytes, dtype, hip_stream, true, cfg);
 }
 
 salt_status salt_serve_trace(const salt_server_config *cfg, const salt_request *requests, int32_t count,

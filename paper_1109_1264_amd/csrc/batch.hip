@@ -1,180 +1,21 @@
-// batch.hip -- many independent expression evaluations (and dot products)
-// of uneven length in one persistent launch.
-//
-// Every item is cut into the reduction's fixed tiles (reduce_common.hpp),
-// and the tiles of all items form one flat list. A grid of workgroups walks
-// that list (grid-stride), so a 2^20-element item and a 64-element item cost
-// in proportion to their tiles, and one launch replaces thousands. In each
-// tile a lane loads its chunks of every operand in bursts, evaluates the tree
-// and stores the result (the paper's load / operate / store packages,
-// Sec. 4.3), and, when the item asks for it, accumulates dot(operand 0,
-// operand 1) from the same registers: the operands are read once for both.
-// The dot's accumulation order inside a tile and the combine over the item's
-// tiles are exactly those of salt_dot, so an item's dot has the same bits in
-// a batch as alone. A second small kernel combines each item's partials, one
-// wave per item.
+// batch.hip -- dispatch of the batched kernels (batch_kernels.hpp) by
+// element type and catalogue tree.
 #include "batch.hpp"
-#include "device.hpp"
 #include "expr.hpp"
-#include "reduce_common.hpp"
 
 namespace salt {
 
-template <int DT, int NL, int U, int NS>
-struct BChunkCtx {
-    using C = typename Tr<DT>::C;
-    const u32x4 (&raw)[NL][U];
-    const C (&s)[NS];
-    int u, p;
-    template <int K>
-    __device__ __forceinline__ C ld() const { return Tr<DT>::get(raw[K][u], p); }
-    template <int J>
-    __device__ __forceinline__ C sc() const { return s[J]; }
-};
-
-template <class E, int DT, int UR, bool NT, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_batch(const DevItem *__restrict__ items,
-                                                  const int32_t *__restrict__ tile_item, int64_t total_tiles,
-                                                  double *ws) {
-    using C = typename Tr<DT>::C;
-    constexpr int V = Tr<DT>::V;
-    constexpr int64_t T = tile_elems<DT>();
-    constexpr int NL = E::n_loads > 0 ? E::n_loads : 1;
-    constexpr int NS = E::n_scal > 0 ? E::n_scal : 1;
-    static_assert(!DOT || E::n_loads >= 2, "dot needs two operands");
-    __shared__ double lds[kBlock / 64];
-    for (int64_t gt = blockIdx.x; gt < total_tiles; gt += gridDim.x) {
-        const int k = __builtin_amdgcn_readfirstlane(tile_item[gt]);
-        const DevItem &it = items[k];
-        const int64_t n = it.n;
-        const int64_t t = gt - it.tile_begin;
-        const bool vec = it.vec != 0;
-        const bool full = vec && (t + 1) * T <= n;
-        const void *op[NL];
-#pragma unroll
-        for (int q = 0; q < NL; ++q) op[q] = it.ops[q];
-        C s[NS];
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            if constexpr (DT == SALT_F64) s[j] = it.sc64[j];
-            else s[j] = it.sc32[j];
-        }
-        void *const out = it.out;
-        Acc<DT> acc[V];
-        const int64_t c0 = t * ((int64_t)kBlock * kChunksPerLane) + threadIdx.x;
-#pragma unroll
-        for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
-            u32x4 raw[NL][UR];
-#pragma unroll
-            for (int q = 0; q < E::n_loads; ++q)
-#pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
-                    raw[q][u] = full ? ld16<NT>((const u32x4 *)op[q] + ci)
-                                     : load_chunk_guarded<DT, NT>(op[q], ci, n, vec);
-                }
-            if (out) {
-#pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    C r[V];
-#pragma unroll
-                    for (int p = 0; p < V; ++p) r[p] = E::ev(BChunkCtx<DT, NL, UR, NS>{raw, s, u, p});
-                    const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
-                    if (full || (vec && (ci + 1) * V <= n)) {
-                        st16<NT>((u32x4 *)out + ci, Tr<DT>::template pack<V>(r));
-                    } else {
-#pragma unroll
-                        for (int p = 0; p < V; ++p)
-                            if (ci * V + p < n) Tr<DT>::st1(out, ci * V + p, r[p]);
-                    }
-                }
-            }
-            if constexpr (DOT) {
-#pragma unroll
-                for (int u = 0; u < UR; ++u)
-#pragma unroll
-                    for (int p = 0; p < V; ++p)
-                        acc[p].add(Tr<DT>::get(raw[0][u], p), Tr<DT>::get(raw[1][u], p));
-            }
-        }
-        if constexpr (DOT) {
-            if (it.dot_out) {
-                const double v = block_sum<kBlock / 64>(lane_value<DT>(acc), lds);
-                if (threadIdx.x == 0) ws[gt] = v;
-            }
-        }
-    }
-}
-
-// One wave per item: the combine of salt_dot's pass 2, wave-serialised.
-template <int DT>
-__global__ __launch_bounds__(kBlock) void k_batch_combine(const DevItem *__restrict__ items, int count,
-                                                          const double *ws) {
-    constexpr int64_t T = tile_elems<DT>();
-    constexpr int kWaves = kBlock / 64;
-    for (int k = blockIdx.x * kWaves + (threadIdx.x >> 6); k < count; k += gridDim.x * kWaves) {
-        const DevItem &it = items[k];
-        if (!it.dot_out) continue;
-        const double r = combine_partials_wave(ws + it.tile_begin, (it.n + T - 1) / T);
-        if ((threadIdx.x & 63) == 0) store_result<DT, false>(it.dot_out, r);
-    }
-}
-
-template <class E, int DT, int UR, bool NT, bool DOT>
-static int launch_batch_u(const BatchLaunch &L) {
-    int64_t grid = L.blocks > 0 && L.blocks < L.total_tiles ? L.blocks : L.total_tiles;
-    if (grid > 0x7fffffff) grid = 0x7fffffff;
-    if (grid > 0)
-        hipLaunchKernelGGL((k_batch<E, DT, UR, NT, DOT>), dim3((unsigned)grid), dim3(kBlock), 0,
-                           (hipStream_t)L.stream, L.items, L.tile_item, L.total_tiles, L.ws);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !DOT || L.count == 0) return (int)e;
-    const int waves = kBlock / 64;
-    const int cgrid = (L.count + waves - 1) / waves < 4096 ? (L.count + waves - 1) / waves : 4096;
-    hipLaunchKernelGGL((k_batch_combine<DT>), dim3(cgrid), dim3(kBlock), 0, (hipStream_t)L.stream,
-                       L.items, L.count, (const double *)L.ws);
-    return (int)hipGetLastError();
-}
-
-template <class E, int DT, bool DOT>
-static int launch_batch_dot(const BatchLaunch &L) {
-    const bool nt = L.nontemporal != 0;
-    switch (L.unroll) {
-        case 2: return nt ? launch_batch_u<E, DT, 2, true, DOT>(L) : launch_batch_u<E, DT, 2, false, DOT>(L);
-        case 4: return nt ? launch_batch_u<E, DT, 4, true, DOT>(L) : launch_batch_u<E, DT, 4, false, DOT>(L);
-        case 8: return nt ? launch_batch_u<E, DT, 8, true, DOT>(L) : launch_batch_u<E, DT, 8, false, DOT>(L);
-        case 16: return nt ? launch_batch_u<E, DT, 16, true, DOT>(L) : launch_batch_u<E, DT, 16, false, DOT>(L);
-        default: return (int)hipErrorInvalidValue;
-    }
-}
-
-template <class E, int DT>
-static int launch_batch(const BatchLaunch &L) {
-    if constexpr (E::n_loads >= 2) {
-        if (L.any_dot) return launch_batch_dot<E, DT, true>(L);
-    } else {
-        if (L.any_dot) return (int)hipErrorInvalidValue;
-    }
-    return launch_batch_dot<E, DT, false>(L);
-}
-
-template <class E>
-static BatchFn batch_fn(int dtype) {
-    switch (dtype) {
-        case SALT_F64: return &launch_batch<E, SALT_F64>;
-        case SALT_F32: return &launch_batch<E, SALT_F32>;
-        case SALT_BF16: return &launch_batch<E, SALT_BF16>;
-        case SALT_F16: return &launch_batch<E, SALT_F16>;
-        default: return nullptr;
-    }
-}
+BatchFn batch_launcher_f64(int id);
+BatchFn batch_launcher_f32(int id);
+BatchFn batch_launcher_bf16(int id);
+BatchFn batch_launcher_f16(int id);
 
 BatchFn catalogue_batch_launcher(int id, int dtype) {
-    switch (id) {
-#define SALT_CAT_CASE(name, ...) \
-    case cat::id_##name: return batch_fn<cat::name>(dtype);
-        SALT_CATALOGUE(SALT_CAT_CASE)
-#undef SALT_CAT_CASE
+    switch (dtype) {
+        case SALT_F64: return batch_launcher_f64(id);
+        case SALT_F32: return batch_launcher_f32(id);
+        case SALT_BF16: return batch_launcher_bf16(id);
+        case SALT_F16: return batch_launcher_f16(id);
         default: return nullptr;
     }
 }

@@ -1,0 +1,7 @@
+// batch_bf16.hip -- the batched kernels for one element type (compiled
+// separately so the types build in parallel).
+#include "batch_kernels.hpp"
+
+namespace salt {
+BatchFn batch_launcher_bf16(int id) { return batch_launcher_for<SALT_BF16>(id); }
+}  // namespace salt

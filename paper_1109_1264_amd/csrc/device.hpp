@@ -49,6 +49,8 @@ struct Tr<SALT_F64> {
     }
     __device__ __forceinline__ static C ld1(const void *p, int64_t i) { return ((const S *)p)[i]; }
     __device__ __forceinline__ static void st1(void *p, int64_t i, C v) { ((S *)p)[i] = v; }
+    // The value a store would keep (storage equals compute type here).
+    __device__ __forceinline__ static C round(C v) { return v; }
 };
 
 template <>
@@ -70,6 +72,7 @@ struct Tr<SALT_F32> {
     }
     __device__ __forceinline__ static C ld1(const void *p, int64_t i) { return ((const S *)p)[i]; }
     __device__ __forceinline__ static void st1(void *p, int64_t i, C v) { ((S *)p)[i] = v; }
+    __device__ __forceinline__ static C round(C v) { return v; }
 };
 
 // bfloat16: the top half of a binary32 pattern.
@@ -103,6 +106,10 @@ struct Tr<SALT_BF16> {
     __device__ __forceinline__ static void st1(void *p, int64_t i, C v) {
         ((S *)p)[i] = __builtin_bit_cast(uint16_t, (__bf16)v);
     }
+    // The value a store would keep: rounded to bfloat16, widened back.
+    __device__ __forceinline__ static C round(C v) {
+        return __uint_as_float((unsigned)__builtin_bit_cast(uint16_t, (__bf16)v) << 16);
+    }
 };
 
 // binary16.
@@ -127,6 +134,7 @@ struct Tr<SALT_F16> {
     __device__ __forceinline__ static void st1(void *p, int64_t i, C v) {
         ((_Float16 *)p)[i] = (_Float16)v;
     }
+    __device__ __forceinline__ static C round(C v) { return (float)(_Float16)v; }
 };
 
 // 16-byte loads and stores, optionally non-temporal (streaming data that is

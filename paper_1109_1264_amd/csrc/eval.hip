@@ -16,11 +16,12 @@
 //  * k_eval_tree<E, ...>: the tree E is a compile-time type (expr.hpp) and the
 //    kernel is straight-line code for it (ahead-of-time catalogue).
 //  * k_eval_interp<...>: any valid program. The program is uniform across the
-//    grid, so its instruction loop runs on the scalar unit; each instruction
-//    code names its stack slot, so the per-lane stack is a register array
-//    indexed by constants inside each case of the switch.
+//    grid, so its instruction loop runs on the scalar unit; the top of the
+//    per-lane stack stays in registers and the rest lives in LDS
+//    (interp.hpp).
 #include "device.hpp"
 #include "expr.hpp"
+#include "interp.hpp"
 #include "launch.hpp"
 
 namespace salt {
@@ -99,85 +100,35 @@ __global__ __launch_bounds__(kBlock) void k_eval_tree(EvalArgs<DT> a) {
 }
 
 // ---------------------------------------------------------------------------
-// generic interpreter
+// generic interpreter (interp.hpp)
 // ---------------------------------------------------------------------------
 
-struct InterpProg {
-    uint8_t code[SALT_MAX_TOKENS];
-    uint8_t sarg[SALT_MAX_TOKENS];
-    int32_t len;
-    int32_t n_loads;
-};
-
-#define SALT_S8(M, k) M(k, 0) M(k, 1) M(k, 2) M(k, 3) M(k, 4) M(k, 5) M(k, 6) M(k, 7)
-#define SALT_K8(M) SALT_S8(M, 0) SALT_S8(M, 1) SALT_S8(M, 2) SALT_S8(M, 3) \
-    SALT_S8(M, 4) SALT_S8(M, 5) SALT_S8(M, 6) SALT_S8(M, 7)
-#define SALT_SLOTS7(M, op) M(op, 0) M(op, 1) M(op, 2) M(op, 3) M(op, 4) M(op, 5) M(op, 6)
-
-// Run program `g` for EL elements per lane; get(k, j) yields element j of
-// operand k. The result ends in st[0].
-template <int EL, class C, class Get>
-__device__ __forceinline__ void interp_run(const InterpProg &g, const C *sc, const Get &get,
-                                           C (&st)[SALT_MAX_STACK][EL]) {
-    for (int t = 0; t < g.len; ++t) {
-        // The program is the same for every lane: say so, so that the switch
-        // is a scalar branch rather than a divergent one.
-        switch (__builtin_amdgcn_readfirstlane(g.code[t])) {
-#define SALT_LOAD_CASE(k, s)                                   \
-    case (k) * 8 + (s): {                                      \
-        _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = get(k, j); \
-    } break;
-            SALT_K8(SALT_LOAD_CASE)
-#undef SALT_LOAD_CASE
-#define SALT_SCALAR_CASE(z, s)                                 \
-    case 64 + (s): {                                           \
-        const C v = sc[__builtin_amdgcn_readfirstlane(g.sarg[t])]; \
-        _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = v; \
-    } break;
-            SALT_S8(SALT_SCALAR_CASE, 0)
-#undef SALT_SCALAR_CASE
-#define SALT_ADD_CASE(z, s) \
-    case 72 + (s): { _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = st[s][j] + st[s + 1][j]; } break;
-#define SALT_SUB_CASE(z, s) \
-    case 80 + (s): { _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = st[s][j] - st[s + 1][j]; } break;
-#define SALT_MUL_CASE(z, s) \
-    case 88 + (s): { _Pragma("unroll") for (int j = 0; j < EL; ++j) st[s][j] = st[s][j] * st[s + 1][j]; } break;
-            SALT_SLOTS7(SALT_ADD_CASE, 0)
-            SALT_SLOTS7(SALT_SUB_CASE, 0)
-            SALT_SLOTS7(SALT_MUL_CASE, 0)
-#undef SALT_ADD_CASE
-#undef SALT_SUB_CASE
-#undef SALT_MUL_CASE
-            default:
-                break;
-        }
-    }
-}
-
-template <int DT, int U, bool NT>
+template <int DT, int U, bool NT, int NL>
 __global__ __launch_bounds__(kBlock) void k_eval_interp(EvalArgs<DT> a, InterpProg g) {
     using C = typename Tr<DT>::C;
     constexpr int V = Tr<DT>::V;
+    extern __shared__ __align__(16) unsigned char interp_smem[];
+    C *lds = (C *)interp_smem;
     constexpr int64_t tile = (int64_t)kBlock * U * V;
     const int64_t n_tiles = a.vec ? a.n / tile : 0;
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const int64_t c0 = t * (kBlock * U) + threadIdx.x;
-        u32x4 raw[SALT_MAX_OPERANDS][U];
+        u32x4 raw[NL][U];
 #pragma unroll
-        for (int k = 0; k < SALT_MAX_OPERANDS; ++k)
+        for (int k = 0; k < NL; ++k)
             if (k < g.n_loads)
 #pragma unroll
                 for (int u = 0; u < U; ++u) raw[k][u] = ld16<NT>((const u32x4 *)a.ops[k] + c0 + u * kBlock);
-        C st[SALT_MAX_STACK][U * V];
-        interp_run<U * V>(g, a.sc, [&](int k, int j) { return Tr<DT>::get(raw[k][j / V], j % V); }, st);
+        C tos[U * V];
+        interp_run<U * V, NL>(g, a.sc, [&](int k, int j) { return Tr<DT>::get(raw[k][j / V], j % V); }, tos, lds);
 #pragma unroll
-        for (int u = 0; u < U; ++u) st16<NT>((u32x4 *)a.out + c0 + u * kBlock, Tr<DT>::template pack<V>(&st[0][u * V]));
+        for (int u = 0; u < U; ++u) st16<NT>((u32x4 *)a.out + c0 + u * kBlock, Tr<DT>::template pack<V>(&tos[u * V]));
     }
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = n_tiles * tile + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += stride) {
-        C st[SALT_MAX_STACK][1];
-        interp_run<1>(g, a.sc, [&](int k, int) { return Tr<DT>::ld1(a.ops[k], i); }, st);
-        Tr<DT>::st1(a.out, i, st[0][0]);
+        C tos[1];
+        interp_run<1, NL>(g, a.sc, [&](int k, int) { return Tr<DT>::ld1(a.ops[k], i); }, tos, lds);
+        Tr<DT>::st1(a.out, i, tos[0]);
     }
 }
 
@@ -271,37 +222,48 @@ int catalogue_program(int id, uint32_t *tokens, int cap, const char **name) {
     return len;
 }
 
-template <int DT, int U, bool NT>
-static hipError_t launch_interp_u(const EvalLaunch &L, const InterpProg &g) {
-    hipLaunchKernelGGL((k_eval_interp<DT, U, NT>), grid_for<DT>(L, U), dim3(kBlock), 0,
+template <int DT, int U, bool NT, int NL>
+static hipError_t launch_interp_u(const EvalLaunch &L, const InterpProg &g, int need) {
+    const size_t lds = interp_lds_bytes(need, U * Tr<DT>::V, sizeof(typename Tr<DT>::C));
+    hipLaunchKernelGGL((k_eval_interp<DT, U, NT, NL>), grid_for<DT>(L, U), dim3(kBlock), lds,
                        (hipStream_t)L.stream, make_args<DT>(L), g);
     return hipGetLastError();
 }
 
-// The interpreter keeps 8 stack slots of U*V values per lane in registers.
-// U is fixed per type: 2 chunks for binary64 and binary32, 1 chunk for 16-bit
-// storage, the shapes that compile without register spills (one chunk of
-// binary64 or binary32 per slot makes the compiler spill).
-template <int DT>
-static hipError_t launch_interp_dt(const EvalLaunch &L, const InterpProg &g) {
-    constexpr int U = Tr<DT>::V >= 8 ? 1 : 2;
+template <int DT, int U>
+static hipError_t launch_interp_nl(const EvalLaunch &L, const InterpProg &g, int nl, int need) {
     const bool nt = L.nontemporal != 0;
-    return nt ? launch_interp_u<DT, U, true>(L, g) : launch_interp_u<DT, U, false>(L, g);
+    switch (nl) {
+        case 2: return nt ? launch_interp_u<DT, U, true, 2>(L, g, need) : launch_interp_u<DT, U, false, 2>(L, g, need);
+        case 4: return nt ? launch_interp_u<DT, U, true, 4>(L, g, need) : launch_interp_u<DT, U, false, 4>(L, g, need);
+        default: return nt ? launch_interp_u<DT, U, true, 8>(L, g, need) : launch_interp_u<DT, U, false, 8>(L, g, need);
+    }
+}
+
+// U, the chunks per lane that one run of the program covers, is the launch
+// knob's unroll (1, 2 or 4; 8 runs as 4), lowered until the LDS stack fits;
+// NL, the operand registers, is the smallest of 2, 4, 8 covering the
+// program.
+template <int DT>
+static hipError_t launch_interp_dt(const EvalLaunch &L, const InterpProg &g, int nl, int need) {
+    const int u = interp_fit_unroll(L.unroll > 4 ? 4 : L.unroll, need, Tr<DT>::V, sizeof(typename Tr<DT>::C));
+    if (u >= 4) return launch_interp_nl<DT, 4>(L, g, nl, need);
+    if (u == 2) return launch_interp_nl<DT, 2>(L, g, nl, need);
+    return launch_interp_nl<DT, 1>(L, g, nl, need);
 }
 
 hipError_t launch_interp(const EvalLaunch &L, const Program &p, int dtype) {
     InterpProg g;
-    for (int t = 0; t < SALT_MAX_TOKENS; ++t) {
-        g.code[t] = t < p.len ? p.code[t] : 0;
-        g.sarg[t] = t < p.len ? p.sarg[t] : 0;
-    }
+    g.clear();
+    for (int t = 0; t < p.len; ++t) g.set(t, p.code[t], p.sarg[t]);
     g.len = p.len;
     g.n_loads = p.n_loads;
+    const int nl = interp_bound(p.n_loads);
     switch (dtype) {
-        case SALT_F64: return launch_interp_dt<SALT_F64>(L, g);
-        case SALT_F32: return launch_interp_dt<SALT_F32>(L, g);
-        case SALT_BF16: return launch_interp_dt<SALT_BF16>(L, g);
-        case SALT_F16: return launch_interp_dt<SALT_F16>(L, g);
+        case SALT_F64: return launch_interp_dt<SALT_F64>(L, g, nl, p.stack_need);
+        case SALT_F32: return launch_interp_dt<SALT_F32>(L, g, nl, p.stack_need);
+        case SALT_BF16: return launch_interp_dt<SALT_BF16>(L, g, nl, p.stack_need);
+        case SALT_F16: return launch_interp_dt<SALT_F16>(L, g, nl, p.stack_need);
         default: return hipErrorInvalidValue;
     }
 }

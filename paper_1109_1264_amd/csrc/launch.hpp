@@ -51,4 +51,21 @@ struct ReduceLaunch {
 int64_t reduce_tile_elems(int dtype);
 hipError_t launch_reduce(const ReduceLaunch &L, int dtype);
 
+// dot / nrm2 of expressions (reduce.hip): operands in the caller's numbering.
+struct ReduceExprLaunch {
+    const void *ops[SALT_MAX_OPERANDS];
+    double sc[SALT_MAX_SCALARS];
+    void *result;
+    double *ws;
+    int64_t n;
+    int32_t vec;
+    uint32_t mask;
+    int32_t unroll;  // chunks per lane per interpreter run: 2, 4, 8
+    int32_t nontemporal;
+    int64_t blocks;
+    int32_t nrm2;
+    void *stream;
+};
+hipError_t launch_reduce_expr(const ReduceExprLaunch &L, const Program &px, const Program *py, int dtype);
+
 }  // namespace salt

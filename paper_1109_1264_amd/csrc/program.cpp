@@ -33,6 +33,7 @@ salt_status compile_program(const uint32_t *prog, int32_t len, int32_t n_operand
     for (int t = 0; t < len; ++t) {
         const uint32_t op = prog[t] & 0xffu, arg = prog[t] >> 8;
         p.sarg[t] = 0;
+        p.sarg_raw[t] = 0;
         if (op == SALT_OP_LOAD) {
             if (arg >= (uint32_t)n_operands)
                 return fail(err, SALT_ERR_PROGRAM, "token %d loads operand %d, out of range", t, (int)arg);
@@ -44,6 +45,8 @@ salt_status compile_program(const uint32_t *prog, int32_t len, int32_t n_operand
             }
             p.canon[t] = SALT_TOKEN(SALT_OP_LOAD, op_canon[arg]);
             p.code[t] = (uint8_t)(op_canon[arg] * 8 + depth);
+            p.code_raw[t] = (uint8_t)(arg * 8 + depth);
+            p.load_mask |= 1u << arg;
             ++depth;
         } else if (op == SALT_OP_SCALAR) {
             if (arg >= (uint32_t)n_scalars)
@@ -56,7 +59,9 @@ salt_status compile_program(const uint32_t *prog, int32_t len, int32_t n_operand
             }
             p.canon[t] = SALT_TOKEN(SALT_OP_SCALAR, sc_canon[arg]);
             p.code[t] = (uint8_t)(kCodeScalar + depth);
+            p.code_raw[t] = p.code[t];
             p.sarg[t] = (uint8_t)sc_canon[arg];
+            p.sarg_raw[t] = (uint8_t)arg;
             ++depth;
         } else if (op == SALT_OP_ADD || op == SALT_OP_SUB || op == SALT_OP_MUL) {
             if (arg != 0)
@@ -65,6 +70,7 @@ salt_status compile_program(const uint32_t *prog, int32_t len, int32_t n_operand
                 return fail(err, SALT_ERR_PROGRAM, "token %d: stack underflow (depth %d)", t, depth);
             p.canon[t] = SALT_TOKEN(op, 0);
             p.code[t] = (uint8_t)(kCodeBinary + 8 * (int)(op - SALT_OP_ADD) + (depth - 2));
+            p.code_raw[t] = p.code[t];
             --depth;
         } else {
             return fail(err, SALT_ERR_PROGRAM, "token %d has unknown opcode %d", t, (int)op);

@@ -35,6 +35,11 @@ struct Program {
     int32_t stack_need = 0;
     uint8_t code[SALT_MAX_TOKENS];    // interpreter codes
     uint8_t sarg[SALT_MAX_TOKENS];    // canonical scalar index for scalar codes
+    // The same codes with the caller's operand and scalar numbers (used when
+    // several programs share one operand list), and the operands read.
+    uint8_t code_raw[SALT_MAX_TOKENS];
+    uint8_t sarg_raw[SALT_MAX_TOKENS];
+    uint32_t load_mask = 0;           // bit k: caller operand k is read
 };
 
 // Validate `prog` against the operand and scalar counts and compile it.

@@ -1,0 +1,10 @@
+// reduce_f32.hip -- the reduction kernels for one element type (compiled
+// separately so the types build in parallel).
+#include "reduce_kernels.hpp"
+
+namespace salt {
+hipError_t launch_reduce_f32(const ReduceLaunch &L) { return launch_reduce_dt<SALT_F32>(L); }
+hipError_t launch_reduce_expr_f32(const ReduceExprLaunch &L, const Program &px, const Program *py) {
+    return launch_reduce_expr_dt<SALT_F32>(L, px, py);
+}
+}  // namespace salt

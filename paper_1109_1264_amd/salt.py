@@ -92,6 +92,10 @@ def lib() -> ctypes.CDLL:
         "salt_status_string": ([I32], ctypes.c_char_p),
         "salt_last_error": ([], ctypes.c_char_p),
         "salt_version": ([], I32),
+        "salt_dot_expr": ([U32P, I32, U32P, I32, P, I32, P, I32, I64, P, P, SZ, I32, P], I32),
+        "salt_nrm2_expr": ([U32P, I32, P, I32, P, I32, I64, P, P, SZ, I32, P], I32),
+        "salt_dot_expr_ex": ([U32P, I32, U32P, I32, P, I32, P, I32, I64, P, P, SZ, I32, P, CFG], I32),
+        "salt_nrm2_expr_ex": ([U32P, I32, P, I32, P, I32, I64, P, P, SZ, I32, P, CFG], I32),
         "salt_batch_plan_create": ([U32P, I32, I32, I32, ctypes.POINTER(BatchItem), I32, I32,
                                     ctypes.POINTER(P)], I32),
         "salt_batch_plan_info": ([P, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(I64)], I32),
@@ -268,6 +272,51 @@ def salt_nrm2(x, n: int | None = None, result=None, ws=None, stream=None, config
     else:
         st = L.salt_nrm2_ex(n, _dev(x), _dev(result), _dev(ws), nb, d, _stream_ptr(stream), _cfg(config))
     check(st)
+    return result
+
+
+def salt_dot_expr(prog_x, prog_y, operands, scalars, n: int | None = None, result=None, ws=None,
+                  stream=None, config=None):
+    """Device scalar sum P_i * Q_i for two programs over one operand list,
+    in one pass (no vector is written)."""
+    d = dtype_code(operands[0])
+    for t in operands:
+        if dtype_code(t) != d:
+            raise TypeError("all operands must share a dtype")
+    if n is None:
+        n = operands[0].numel()
+    result = _result_tensor(d, operands[0].device) if result is None else result
+    ws = workspace(n, d, operands[0].device) if ws is None else ws
+    px, lx = _prog(prog_x)
+    py, ly = _prog(prog_y)
+    ops = (ctypes.c_void_p * max(1, len(operands)))(*[_dev(t) for t in operands])
+    sc = (ctypes.c_double * max(1, len(scalars)))(*[float(s) for s in scalars])
+    args = (px, lx, py, ly, ops, len(operands), sc, len(scalars), n, _dev(result), _dev(ws),
+            ws.numel() * ws.element_size(), d, _stream_ptr(stream))
+    if config is None:
+        check(lib().salt_dot_expr(*args))
+    else:
+        check(lib().salt_dot_expr_ex(*args, _cfg(config)))
+    return result
+
+
+def salt_nrm2_expr(prog, operands, scalars, n: int | None = None, result=None, ws=None, stream=None,
+                   config=None):
+    """Device scalar sqrt(sum P_i^2) of a program, in one pass."""
+    d = dtype_code(operands[0])
+    if n is None:
+        n = operands[0].numel()
+    result = _result_tensor(d, operands[0].device) if result is None else result
+    ws = workspace(n, d, operands[0].device) if ws is None else ws
+    p, lp = _prog(prog)
+    ops = (ctypes.c_void_p * max(1, len(operands)))(*[_dev(t) for t in operands])
+    sc = (ctypes.c_double * max(1, len(scalars)))(*[float(s) for s in scalars])
+    args = (p, lp, ops, len(operands), sc, len(scalars), n, _dev(result), _dev(ws),
+            ws.numel() * ws.element_size(), d, _stream_ptr(stream))
+    if config is None:
+        check(lib().salt_nrm2_expr(*args))
+    else:
+        check(lib().salt_nrm2_expr_ex(*args, _cfg(config)))
     return result
 
 

@@ -206,3 +206,26 @@ def test_tuning_table(tmp_path):
             empty = tmp_path / "empty.txt"
             empty.write_text("")
             S.salt_tuning_load(str(empty))
+
+
+def test_reduce_expr_argument_errors(L):
+    X, Y, R, W = 0x100000, 0x200000, 0x300000, 0x400000
+    n = 100000
+    need = S.salt_reduce_workspace_bytes(n, S.F64)
+    px = (ctypes.c_uint32 * 1)(T(S.LOAD, 0))
+    py = (ctypes.c_uint32 * 1)(T(S.LOAD, 1))
+    bad = (ctypes.c_uint32 * 1)(T(S.ADD))
+    ops = (ctypes.c_void_p * 2)(X, Y)
+    ops_null = (ctypes.c_void_p * 2)(X, None)
+    sc = (ctypes.c_double * 1)(1.0)
+    f = L.salt_dot_expr
+    assert f(bad, 1, py, 1, ops, 2, sc, 0, n, R, W, need, S.F64, None) == S.ERR_PROGRAM
+    assert b"first program" in L.salt_last_error()
+    assert f(px, 1, bad, 1, ops, 2, sc, 0, n, R, W, need, S.F64, None) == S.ERR_PROGRAM
+    assert f(px, 1, py, 1, ops_null, 2, sc, 0, n, R, W, need, S.F64, None) == S.ERR_ARG
+    assert f(px, 1, py, 1, ops, 2, sc, 0, n, None, W, need, S.F64, None) == S.ERR_ARG
+    assert f(px, 1, py, 1, ops, 2, sc, 0, n, R, W, need - 8, S.F64, None) == S.ERR_WORKSPACE
+    assert f(px, 1, py, 1, ops, 2, sc, 0, -1, R, W, need, S.F64, None) == S.ERR_ARG
+    assert L.salt_nrm2_expr(px, 1, ops, 2, sc, 0, n, R, X + 8, need, S.F64, None) == S.ERR_WORKSPACE
+    deep = (ctypes.c_uint32 * 15)(*([T(S.LOAD, 0)] * 8 + [T(S.SUB)] * 7))
+    assert f(deep, 15, deep, 15, ops, 2, sc, 0, n, R, W, need, S.F64, None) == S.ERR_UNSUPPORTED

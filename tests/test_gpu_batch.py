@@ -90,7 +90,7 @@ def test_batch_launch_shapes_same_bits():
     torch.cuda.synchronize()
     ref_out = [to_host_bits(it["out"], dtype) for it in items]
     ref_dot = [float(it["dot_out"].item()) for it in items]
-    for unroll in (2, 4, 8, 16):
+    for unroll in (2, 4, 8):
         for nt in (0, 1):
             for blocks in (0, 1, 7, 256):
                 for it in items:
