@@ -299,7 +299,7 @@ struct salt_batch_plan_s {
     int64_t total_tiles = 0, total_elems = 0;
     bool any_dot = false;
     std::vector<salt::DevItem> items;
-    std::vector<int32_t> tile_item;
+    std::vector<salt::TileRef> tiles;
     size_t table_bytes = 0, ws_bytes = 0;
     void *table = nullptr;
 };
@@ -330,7 +330,7 @@ salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, v
     if (!fn) return fail(SALT_ERR_UNSUPPORTED, "no batched kernel for this tree and dtype");
     BatchLaunch L;
     L.items = (const DevItem *)plan->table;
-    L.tile_item = (const int32_t *)((const char *)plan->table + sizeof(DevItem) * plan->count);
+    L.tiles = (const TileRef *)((const char *)plan->table + sizeof(DevItem) * plan->count);
     L.total_tiles = plan->total_tiles;
     L.count = plan->count;
     L.any_dot = plan->any_dot ? 1 : 0;
@@ -577,7 +577,7 @@ salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len, int32
                 delete pl;
                 return fail(SALT_ERR_UNSUPPORTED, "too many tiles in one batch");
             }
-            for (int64_t t = 0; t < nt; ++t) pl->tile_item.push_back(i);
+            for (int64_t t = 0; t < nt; ++t) pl->tiles.push_back(TileRef{i, (int32_t)t});
             tiles += nt;
             pl->total_elems += it.n;
             pl->items[i] = d;
@@ -587,7 +587,8 @@ salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len, int32
         return fail(SALT_ERR_ARG, "out of host memory");
     }
     pl->total_tiles = tiles;
-    pl->table_bytes = round_up(sizeof(DevItem) * (size_t)count + sizeof(int32_t) * (size_t)tiles, 256);
+    order_tiles(pl->tiles.data(), tiles, pl->items.data(), T);
+    pl->table_bytes = round_up(sizeof(DevItem) * (size_t)count + sizeof(TileRef) * (size_t)tiles, 256);
     pl->ws_bytes = pl->any_dot ? sizeof(double) * (size_t)tiles : 0;
     *plan = pl;
     return SALT_OK;
@@ -608,8 +609,8 @@ salt_status salt_batch_upload(salt_batch_plan plan, void *table, size_t table_by
     if (table_bytes < plan->table_bytes) return fail(SALT_ERR_ARG, "table buffer too small");
     std::vector<char> host(plan->table_bytes, 0);
     std::memcpy(host.data(), plan->items.data(), sizeof(DevItem) * plan->items.size());
-    std::memcpy(host.data() + sizeof(DevItem) * plan->items.size(), plan->tile_item.data(),
-                sizeof(int32_t) * plan->tile_item.size());
+    std::memcpy(host.data() + sizeof(DevItem) * plan->items.size(), plan->tiles.data(),
+                sizeof(TileRef) * plan->tiles.size());
     if (plan->table_bytes > 0) {
         hipError_t e = hipMemcpyAsync(table, host.data(), plan->table_bytes, hipMemcpyHostToDevice,
                                       (hipStream_t)hip_stream);

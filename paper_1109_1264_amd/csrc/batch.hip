@@ -1,5 +1,7 @@
 // batch.hip -- dispatch of the batched kernels (batch_kernels.hpp) by
 // element type and catalogue tree.
+#include <algorithm>
+
 #include "batch.hpp"
 #include "expr.hpp"
 
@@ -18,6 +20,14 @@ BatchFn catalogue_batch_launcher(int id, int dtype) {
         case SALT_F16: return batch_launcher_f16(id);
         default: return nullptr;
     }
+}
+
+void order_tiles(TileRef *refs, int64_t count, const DevItem *items, int64_t tile_elems) {
+    auto weight = [&](const TileRef &r) {
+        const int64_t rest = items[r.item].n - (int64_t)r.tile * tile_elems;
+        return rest < tile_elems ? rest : tile_elems;
+    };
+    std::stable_sort(refs, refs + count, [&](const TileRef &a, const TileRef &b) { return weight(a) > weight(b); });
 }
 
 int catalogue_loads(int id) {

@@ -24,10 +24,22 @@ struct alignas(16) DevItem {
 };
 static_assert(sizeof(DevItem) == 256, "descriptor layout");
 
+// One entry of the execution list: tile `tile` of item `item`. Its partial
+// goes to ws[items[item].tile_begin + tile], whatever its place in the list.
+struct TileRef {
+    int32_t item;
+    int32_t tile;
+};
+
+// Order of the execution list: full tiles first, then the items' ragged last
+// tiles by decreasing length (longest processing time first), so the grid's
+// last workgroups are the light ones.
+void order_tiles(TileRef *refs, int64_t count, const DevItem *items, int64_t tile_elems);
+
 // Host-side launch of the batched kernels for one (tree, dtype).
 struct BatchLaunch {
     const DevItem *items;
-    const int32_t *tile_item;  // global tile -> item
+    const TileRef *tiles;  // execution list
     int64_t total_tiles;
     int32_t count;
     int32_t any_dot;

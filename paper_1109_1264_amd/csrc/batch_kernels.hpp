@@ -34,9 +34,134 @@ struct BChunkCtx {
     __device__ __forceinline__ C sc() const { return s[J]; }
 };
 
+// Operand and output pointers of an item are read from its descriptor in
+// memory, so the compiler cannot tell their address space and would emit flat
+// memory instructions (which also count against the LDS/scalar wait counter
+// and force full waits). These name the global address space.
+using gu32x4 = __attribute__((address_space(1))) u32x4;
+template <bool NT>
+__device__ __forceinline__ u32x4 gld16(const void *p, int64_t ci) {
+    const gu32x4 *g = (const gu32x4 *)p + ci;
+    if constexpr (NT) return __builtin_nontemporal_load(g);
+    else return *g;
+}
+template <bool NT>
+__device__ __forceinline__ void gst16(void *p, int64_t ci, u32x4 v) {
+    gu32x4 *g = (gu32x4 *)p + ci;
+    if constexpr (NT) __builtin_nontemporal_store(v, g);
+    else *g = v;
+}
+
+// Raw buffer resource over `bytes` bytes from p (stride 0; the last word is
+// the gfx9-family data-format field). The hardware checks every access
+// against the size: loads past it return zero and stores past it are dropped,
+// so a ragged tile needs no per-chunk branches.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+template <bool NT>
+__device__ __forceinline__ u32x4 bld16(__amdgpu_buffer_rsrc_t r, int32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? 2 : 0);
+}
+template <bool NT>
+__device__ __forceinline__ void bst16(__amdgpu_buffer_rsrc_t r, int32_t off, u32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, NT ? 2 : 0);
+}
+
+// Shape of one tile of one item.
+enum TileForm {
+    kWhole = 0,    // inside the item, arrays aligned: plain 16-byte accesses
+    kRagged = 1,   // the item's last tile, arrays aligned: range-checked
+                   // buffer accesses, plus one chunk that straddles the end
+    kUnaligned = 2 // some array not 16-byte aligned: element by element
+};
+
+// One tile of one item. `c0` is this lane's first chunk of the tile, `m` the
+// elements of the item from the tile's start (m >= tile size for kWhole).
+// All forms visit the chunks and accumulate the dot in the same order and
+// read zeros past the end, so the partial is the same whichever form runs.
+template <class E, int DT, int UR, bool NT, bool DOT, int FORM, int NL, int NS>
+__device__ __forceinline__ void batch_tile(const void *const (&op)[NL], const typename Tr<DT>::C (&s)[NS],
+                                           void *out, int64_t n, int64_t t, int64_t m,
+                                           Acc<DT> (&acc)[Tr<DT>::V]) {
+    using C = typename Tr<DT>::C;
+    using S = typename Tr<DT>::S;
+    constexpr int V = Tr<DT>::V;
+    constexpr int64_t T = tile_elems<DT>();
+    const int64_t tile_chunk = t * ((int64_t)kBlock * kChunksPerLane);  // first chunk of the tile
+    const int64_t c0 = tile_chunk + threadIdx.x;
+    // kRagged: whole chunks in range, and the chunk (relative index) that
+    // straddles the end, if any.
+    const int32_t whole = (int32_t)(m / V);
+    const int32_t straddle = (m % V) ? whole : -1;
+    __amdgpu_buffer_rsrc_t rin[NL], rout;
+    if constexpr (FORM == kRagged) {
+#pragma unroll
+        for (int q = 0; q < E::n_loads; ++q) rin[q] = rsrc((const S *)op[q] + t * T, whole * 16);
+        if (out) rout = rsrc((S *)out + t * T, whole * 16);
+    }
+#pragma unroll
+    for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
+        u32x4 raw[NL][UR];
+#pragma unroll
+        for (int q = 0; q < E::n_loads; ++q)
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
+                if constexpr (FORM == kWhole) {
+                    raw[q][u] = gld16<NT>(op[q], ci);
+                } else if constexpr (FORM == kRagged) {
+                    raw[q][u] = bld16<NT>(rin[q], (int32_t)(ci - tile_chunk) * 16);
+                } else {
+                    raw[q][u] = load_chunk_guarded<DT, NT>(op[q], ci, n, false);
+                }
+            }
+        if constexpr (FORM == kRagged) {
+            // The straddling chunk read zeros above; its lane reloads the
+            // elements that exist. The burst and the wave tests are uniform.
+#pragma unroll
+            for (int u = 0; u < UR; ++u)
+                if (straddle >= 0 && it0 + u == straddle / kBlock && (int)threadIdx.x == straddle % kBlock) {
+#pragma unroll
+                    for (int q = 0; q < E::n_loads; ++q)
+                        raw[q][u] = load_chunk_guarded<DT, NT>(op[q], c0 + (int64_t)(it0 + u) * kBlock, n, false);
+                }
+        }
+        if (out) {
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                C r[V];
+#pragma unroll
+                for (int p = 0; p < V; ++p) r[p] = E::ev(BChunkCtx<DT, NL, UR, NS>{raw, s, u, p});
+                const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
+                if constexpr (FORM == kWhole) {
+                    gst16<NT>(out, ci, Tr<DT>::template pack<V>(r));
+                } else if constexpr (FORM == kRagged) {
+                    bst16<NT>(rout, (int32_t)(ci - tile_chunk) * 16, Tr<DT>::template pack<V>(r));
+                    if (straddle >= 0 && it0 + u == straddle / kBlock && (int)threadIdx.x == straddle % kBlock) {
+#pragma unroll
+                        for (int p = 0; p < V; ++p)
+                            if (ci * V + p < n) Tr<DT>::st1(out, ci * V + p, r[p]);
+                    }
+                } else {
+#pragma unroll
+                    for (int p = 0; p < V; ++p)
+                        if (ci * V + p < n) Tr<DT>::st1(out, ci * V + p, r[p]);
+                }
+            }
+        }
+        if constexpr (DOT) {
+#pragma unroll
+            for (int u = 0; u < UR; ++u)
+#pragma unroll
+                for (int p = 0; p < V; ++p) acc[p].add(Tr<DT>::get(raw[0][u], p), Tr<DT>::get(raw[1][u], p));
+        }
+    }
+}
+
 template <class E, int DT, int UR, bool NT, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_batch(const DevItem *__restrict__ items,
-                                                  const int32_t *__restrict__ tile_item, int64_t total_tiles,
+                                                  const TileRef *__restrict__ tiles, int64_t total_tiles,
                                                   double *ws) {
     using C = typename Tr<DT>::C;
     constexpr int V = Tr<DT>::V;
@@ -46,12 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_batch(const DevItem *__restrict__ it
     static_assert(!DOT || E::n_loads >= 2, "dot needs two operands");
     __shared__ double lds[kBlock / 64];
     for (int64_t gt = blockIdx.x; gt < total_tiles; gt += gridDim.x) {
-        const int k = __builtin_amdgcn_readfirstlane(tile_item[gt]);
+        const int k = __builtin_amdgcn_readfirstlane(tiles[gt].item);
+        const int64_t t = __builtin_amdgcn_readfirstlane(tiles[gt].tile);
         const DevItem &it = items[k];
         const int64_t n = it.n;
-        const int64_t t = gt - it.tile_begin;
         const bool vec = it.vec != 0;
-        const bool full = vec && (t + 1) * T <= n;
         const void *op[NL];
 #pragma unroll
         for (int q = 0; q < NL; ++q) op[q] = it.ops[q];
@@ -61,48 +185,18 @@ __global__ __launch_bounds__(kBlock) void k_batch(const DevItem *__restrict__ it
             if constexpr (DT == SALT_F64) s[j] = it.sc64[j];
             else s[j] = it.sc32[j];
         }
-        void *const out = it.out;
         Acc<DT> acc[V];
-        const int64_t c0 = t * ((int64_t)kBlock * kChunksPerLane) + threadIdx.x;
-#pragma unroll
-        for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
-            u32x4 raw[NL][UR];
-#pragma unroll
-            for (int q = 0; q < E::n_loads; ++q)
-#pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
-                    raw[q][u] = full ? ld16<NT>((const u32x4 *)op[q] + ci)
-                                     : load_chunk_guarded<DT, NT>(op[q], ci, n, vec);
-                }
-            if (out) {
-#pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    C r[V];
-#pragma unroll
-                    for (int p = 0; p < V; ++p) r[p] = E::ev(BChunkCtx<DT, NL, UR, NS>{raw, s, u, p});
-                    const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
-                    if (full || (vec && (ci + 1) * V <= n)) {
-                        st16<NT>((u32x4 *)out + ci, Tr<DT>::template pack<V>(r));
-                    } else {
-#pragma unroll
-                        for (int p = 0; p < V; ++p)
-                            if (ci * V + p < n) Tr<DT>::st1(out, ci * V + p, r[p]);
-                    }
-                }
-            }
-            if constexpr (DOT) {
-#pragma unroll
-                for (int u = 0; u < UR; ++u)
-#pragma unroll
-                    for (int p = 0; p < V; ++p)
-                        acc[p].add(Tr<DT>::get(raw[0][u], p), Tr<DT>::get(raw[1][u], p));
-            }
-        }
+        const int64_t m = n - t * T;
+        if (!vec)
+            batch_tile<E, DT, UR, NT, DOT, kUnaligned>(op, s, it.out, n, t, m, acc);
+        else if (m >= T)
+            batch_tile<E, DT, UR, NT, DOT, kWhole>(op, s, it.out, n, t, m, acc);
+        else
+            batch_tile<E, DT, UR, NT, DOT, kRagged>(op, s, it.out, n, t, m, acc);
         if constexpr (DOT) {
             if (it.dot_out) {
                 const double v = block_sum<kBlock / 64>(lane_value<DT>(acc), lds);
-                if (threadIdx.x == 0) ws[gt] = v;
+                if (threadIdx.x == 0) ws[it.tile_begin + t] = v;
             }
         }
     }
@@ -128,7 +222,7 @@ static int launch_batch_u(const BatchLaunch &L) {
     if (grid > 0x7fffffff) grid = 0x7fffffff;
     if (grid > 0)
         hipLaunchKernelGGL((k_batch<E, DT, UR, NT, DOT>), dim3((unsigned)grid), dim3(kBlock), 0,
-                           (hipStream_t)L.stream, L.items, L.tile_item, L.total_tiles, L.ws);
+                           (hipStream_t)L.stream, L.items, L.tiles, L.total_tiles, L.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !DOT || L.count == 0) return (int)e;
     const int waves = kBlock / 64;

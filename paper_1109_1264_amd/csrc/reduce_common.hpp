@@ -138,20 +138,33 @@ __device__ __forceinline__ double combine_partials(const double *part, int64_t c
     return block_sum<kFinalBlock / 64>(v, lds);
 }
 
-// The same arithmetic as combine_partials, done by a single wave: it visits
-// the 16 waves of the 1024-lane combine one after another (lane j of virtual
-// wave w plays lane 64*w + j), so the result has the same bits. Used where
-// one workgroup per reduction would be wasteful (many small reductions).
+// The same arithmetic as combine_partials, done by a single wave: lane j of
+// virtual wave v plays lane 64v + j of the 1024-lane combine, the 16 virtual
+// waves' sums go through the same pairwise tree, so the result has the same
+// bits. Used where one workgroup per reduction would be wasteful (many small
+// reductions). Each pass over 1024 partials issues its 16 loads together;
+// slots past `count` add +0, and a virtual wave with no partial sums to +0
+// without being visited: adding +0 leaves any sum that is not -0 unchanged,
+// and these sums never are -0 (they start at +0).
 __device__ __forceinline__ double combine_partials_wave(const double *part, int64_t count) {
     constexpr int W = kFinalBlock / 64;
     const int lane = threadIdx.x & 63;
+    double v[W];
+#pragma unroll
+    for (int vw = 0; vw < W; ++vw) v[vw] = 0.0;
+    for (int64_t base = 0; base < count; base += kFinalBlock) {
+        double q[W];
+#pragma unroll
+        for (int vw = 0; vw < W; ++vw) {
+            const int64_t i = base + vw * 64 + lane;
+            q[vw] = i < count ? part[i] : 0.0;
+        }
+#pragma unroll
+        for (int vw = 0; vw < W; ++vw) v[vw] = v[vw] + q[vw];
+    }
     double w[W];
 #pragma unroll
-    for (int vw = 0; vw < W; ++vw) {
-        double v = 0.0;
-        for (int64_t i = vw * 64 + lane; i < count; i += kFinalBlock) v = v + part[i];
-        w[vw] = wave_sum(v);
-    }
+    for (int vw = 0; vw < W; ++vw) w[vw] = (int64_t)vw * 64 < count ? wave_sum(v[vw]) : 0.0;
 #pragma unroll
     for (int h = W / 2; h >= 1; h >>= 1)
 #pragma unroll

@@ -137,7 +137,8 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                 if (r.n > 0 && !r.operands[k]) why = SALT_ERR_ARG;
             const int64_t T = reduce_tile_elems(r.dtype);
             const int64_t tiles = (r.n + T - 1) / T;
-            if (sizeof(DevItem) + 4 * (size_t)tiles + kMaxGroups * 2 * kAlign > slot_cap) why = SALT_ERR_UNSUPPORTED;
+            if (sizeof(DevItem) + sizeof(TileRef) * (size_t)tiles + kMaxGroups * 2 * kAlign > slot_cap)
+                why = SALT_ERR_UNSUPPORTED;
         }
         if (why != SALT_OK) {
             ok[i] = 0;
@@ -264,7 +265,7 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                 while (!admitted.empty() && (int)take.size() < cfg->max_batch) {
                     const int r = admitted.front();
                     const int64_t T = reduce_tile_elems(reqs[r].dtype);
-                    const size_t add = sizeof(DevItem) + 4 * (size_t)((reqs[r].n + T - 1) / T);
+                    const size_t add = sizeof(DevItem) + sizeof(TileRef) * (size_t)((reqs[r].n + T - 1) / T);
                     if (need + add + kMaxGroups * 2 * kAlign > sl.capacity) break;
                     need += add;
                     take.push_back(r);
@@ -318,11 +319,12 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                     }
                     pos = up(pos + sizeof(DevItem) * g.count, kAlign);
                     g.map_off = pos;
-                    int32_t *map = (int32_t *)(sl.staging + pos);
+                    TileRef *map = (TileRef *)(sl.staging + pos);
                     int64_t t = 0;
                     for (int j = 0; j < g.count; ++j)
-                        for (int64_t q = 0; q < (items[j].n + T - 1) / T; ++q) map[t++] = j;
-                    pos = up(pos + 4 * (size_t)g.tiles, kAlign);
+                        for (int64_t q = 0; q < (items[j].n + T - 1) / T; ++q) map[t++] = TileRef{j, (int32_t)q};
+                    order_tiles(map, g.tiles, items, T);
+                    pos = up(pos + sizeof(TileRef) * (size_t)g.tiles, kAlign);
                     groups.push_back(g);
                     a = b;
                 }
@@ -339,7 +341,7 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                     }
                     BatchLaunch L;
                     L.items = (const DevItem *)(sl.dev_table + g.items_off);
-                    L.tile_item = (const int32_t *)(sl.dev_table + g.map_off);
+                    L.tiles = (const TileRef *)(sl.dev_table + g.map_off);
                     L.total_tiles = g.tiles;
                     L.count = g.count;
                     L.any_dot = 0;

@@ -50,7 +50,8 @@ def test_tiles_table_and_workspace_sizes():
     assert st == S.OK, S.lib().salt_last_error()
     tb, wb, tiles = info(h)
     assert tiles == 0 + 1 + 1 + 2
-    assert tb == ((4 * 256 + 4 * tiles + 255) // 256) * 256
+    # descriptors, then the execution list (item, tile) pairs
+    assert tb == ((4 * 256 + 8 * tiles + 255) // 256) * 256
     assert wb == 8 * tiles
     S.lib().salt_batch_plan_destroy(h)
     # without any dot: no workspace
