@@ -82,6 +82,12 @@ def load(path: str) -> ctypes.CDLL:
     L.oracle_naive_dot_f64.restype = D
     L.oracle_naive_dot_f32.argtypes = [I64, P, P]
     L.oracle_naive_dot_f32.restype = ctypes.c_float
+    L.oracle_copy.argtypes = [I64, P, I64, P, I64, I]
+    L.oracle_copy.restype = I
+    L.oracle_iamax_f64.argtypes = [I64, P, I64]
+    L.oracle_iamax_f64.restype = I64
+    L.oracle_iamax_f32.argtypes = [I64, P, I64]
+    L.oracle_iamax_f32.restype = I64
     L.oracle_widen_h16.argtypes = [I, P, P, I64]
     L.oracle_widen_h16.restype = None
     L.oracle_narrow_h16.argtypes = [I, P, P, I64]
@@ -208,6 +214,85 @@ def naive_dot(x: np.ndarray, y: np.ndarray, dtype: str = "f64") -> float:
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     return float(L.oracle_naive_dot_f64(len(x), _ptr(x), _ptr(y)))
+
+
+# ---------------------------------------------------------------------------
+# BLAS level-1 with increments (reference BLAS conventions): element i of an
+# n-element vector with increment inc is x[i*inc] (inc >= 0) or
+# x[(n-1-i)*|inc|] (inc < 0). The strided operations are gathers into
+# contiguous vectors, the contiguous definitions above, and a scatter back.
+# ---------------------------------------------------------------------------
+
+def blas_span(n: int, inc: int) -> int:
+    """Elements an n-element vector with increment inc spans (>= 1 if n > 0)."""
+    return 0 if n <= 0 else 1 + (n - 1) * abs(inc)
+
+
+def copy(n: int, x: np.ndarray, incx: int, y: np.ndarray, incy: int) -> np.ndarray:
+    """Return a copy of ``y`` with y_i <- x_i (byte for byte)."""
+    x = np.ascontiguousarray(x)
+    out = np.array(y, copy=True)
+    if x.dtype.itemsize != out.dtype.itemsize:
+        raise ValueError("element sizes differ")
+    if n > 0 and (len(x) < blas_span(n, incx) or len(out) < blas_span(n, incy)):
+        raise ValueError("array shorter than the strided vector")
+    if lib().oracle_copy(n, _ptr(x), incx, _ptr(out), incy, out.dtype.itemsize) != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out
+
+
+def gather(n: int, x: np.ndarray, inc: int) -> np.ndarray:
+    """The n elements of a strided vector, contiguous, in element order."""
+    x = np.ascontiguousarray(x)
+    return copy(n, x, inc, np.empty(max(n, 0), dtype=x.dtype), 1)
+
+
+def scatter(n: int, v: np.ndarray, y: np.ndarray, inc: int) -> np.ndarray:
+    """Return a copy of ``y`` with its strided elements replaced by ``v``."""
+    return copy(n, np.ascontiguousarray(v, dtype=np.asarray(y).dtype), 1, y, inc)
+
+
+def scal(n: int, alpha: float, x: np.ndarray, inc: int, dtype: str) -> np.ndarray:
+    """x_i <- alpha*x_i (a new array). inc <= 0: unchanged (reference BLAS)."""
+    x = np.array(x, dtype=_NP[dtype], copy=True)
+    if n <= 0 or inc <= 0:
+        return x
+    v = eval_program([(0 << 8) | SCALAR, (0 << 8) | LOAD, MUL], [gather(n, x, inc)], [alpha], dtype)
+    return scatter(n, v, x, inc)
+
+
+def axpy_strided(n: int, alpha: float, x: np.ndarray, incx: int, y: np.ndarray, incy: int,
+                 dtype: str) -> np.ndarray:
+    """y_i <- alpha*x_i + y_i (a new array)."""
+    y = np.array(y, dtype=_NP[dtype], copy=True)
+    if n <= 0:
+        return y
+    v = axpy(alpha, gather(n, np.asarray(x, dtype=_NP[dtype]), incx), gather(n, y, incy), dtype)
+    return scatter(n, v, y, incy)
+
+
+def asum(x: np.ndarray) -> tuple[float, float]:
+    """sum |x_i| of float64 values (Dot2 against ones), and the same value as
+    the tolerance scale."""
+    a = np.abs(np.ascontiguousarray(x, dtype=np.float64))
+    r, s = dot2(a, np.ones(len(a)))
+    return r, s
+
+
+def iamax(n: int, x: np.ndarray, inc: int, dtype: str) -> int:
+    """Index (from 0) of the first element of largest magnitude; -1 when
+    n < 1 or inc <= 0. 16-bit storage is compared on its exact binary32
+    values."""
+    if n < 1 or inc <= 0:
+        return -1
+    if len(x) < blas_span(n, inc):
+        raise ValueError("array shorter than the strided vector")
+    L = lib()
+    if dtype == "f64":
+        a = np.ascontiguousarray(x, dtype=np.float64)
+        return int(L.oracle_iamax_f64(n, _ptr(a), inc))
+    a = np.ascontiguousarray(x, dtype=np.float32) if dtype == "f32" else widen(x, dtype).astype(np.float32)
+    return int(L.oracle_iamax_f32(n, _ptr(a), inc))
 
 
 # Reduction tolerances, relative to sum |x_i*y_i| of the stored values.

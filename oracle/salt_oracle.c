@@ -28,6 +28,13 @@
  *    sqrt(sum x_i^2), from Dot2(x, x).
  *  - oracle_naive_dot_*: plain sequential loops, kept as a CPU timing baseline
  *    and as the same-precision FP32 mode (not a reference value at large n).
+ *  - oracle_copy, oracle_iamax_*: the BLAS level-1 interface that the paper
+ *    measures against (Sec. 1, the BLAS interface; Sec. 5, the xDOT / xSCAL /
+ *    xAXPY / xCOPY comparisons), with its strided vectors. A BLAS vector of n
+ *    elements with increment inc holds element i at x[i*inc] for inc >= 0
+ *    and at x[(n-1-i)*(-inc)] for inc < 0 (the reference BLAS convention).
+ *    Strided scal, axpy, dot, nrm2 and asum are these gathers followed by the
+ *    contiguous definitions above (composed in oracle/__init__.py).
  *
  * Storage types: binary64 ("f64"), binary32 ("f32"), bfloat16 and binary16
  * held as raw 16-bit patterns. 16-bit storage is widened exactly to binary32,
@@ -276,4 +283,55 @@ float oracle_naive_dot_f32(int64_t n, const float *x, const float *y) {
     float s = 0.0f;
     for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];
     return s;
+}
+
+/* ---- BLAS level-1 with increments ------------------------------------------ */
+
+/* Offset (in elements) of element i of an n-element BLAS vector with
+ * increment inc: i*inc for inc >= 0, (n-1-i)*|inc| for inc < 0. */
+static int64_t blas_offset(int64_t i, int64_t n, int64_t inc) {
+    return inc >= 0 ? i * inc : (n - 1 - i) * (-inc);
+}
+
+/* y_i <- x_i for i < n, elements of `esize` bytes, copied byte for byte. */
+int oracle_copy(int64_t n, const void *x, int64_t incx, void *y, int64_t incy, int esize) {
+    if (n < 0 || esize <= 0) return 1;
+    for (int64_t i = 0; i < n; ++i)
+        memcpy((char *)y + blas_offset(i, n, incy) * esize, (const char *)x + blas_offset(i, n, incx) * esize,
+               (size_t)esize);
+    return 0;
+}
+
+/* Index (from 0) of the first element of largest magnitude, scanning in
+ * order and replacing the candidate only on a strictly larger magnitude, as
+ * the reference BLAS does: a NaN never replaces the candidate, so a NaN is
+ * the answer only when it is element 0. Returns -1 when n < 1 or inc <= 0
+ * (the reference returns 0, its "no element", for these). */
+int64_t oracle_iamax_f64(int64_t n, const double *x, int64_t inc) {
+    if (n < 1 || inc <= 0) return -1;
+    int64_t best = 0;
+    double m = fabs(x[0]);
+    for (int64_t i = 1; i < n; ++i) {
+        const double a = fabs(x[i * inc]);
+        if (a > m) {
+            best = i;
+            m = a;
+        }
+    }
+    return best;
+}
+
+/* The same on binary32 values (16-bit storage is widened first, exactly). */
+int64_t oracle_iamax_f32(int64_t n, const float *x, int64_t inc) {
+    if (n < 1 || inc <= 0) return -1;
+    int64_t best = 0;
+    float m = fabsf(x[0]);
+    for (int64_t i = 1; i < n; ++i) {
+        const float a = fabsf(x[i * inc]);
+        if (a > m) {
+            best = i;
+            m = a;
+        }
+    }
+    return best;
 }

@@ -47,6 +47,19 @@ MUTANTS = {
     # naive loop accumulating in the wrong precision
     "naive_f32_in_f64": ("float s = 0.0f;\n    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];",
                          "double s = 0.0;\n    for (int64_t i = 0; i < n; ++i) s = s + (double)x[i] * y[i];"),
+    # negative increments walking forward instead of from the far end
+    "blas_negative_forward": ("return inc >= 0 ? i * inc : (n - 1 - i) * (-inc);",
+                              "return inc >= 0 ? i * inc : i * (-inc);"),
+    # the last element of a negative-increment vector dropped (off by one)
+    "blas_negative_off_by_one": ("return inc >= 0 ? i * inc : (n - 1 - i) * (-inc);",
+                                 "return inc >= 0 ? i * inc : (n - i) * (-inc) - 1;"),
+    # iamax keeping the last of equal magnitudes
+    "iamax_last_tie": ("        const double a = fabs(x[i * inc]);\n        if (a > m) {",
+                       "        const double a = fabs(x[i * inc]);\n        if (a >= m) {"),
+    # iamax on signed values instead of magnitudes (binary32)
+    "iamax_signed_f32": ("const float a = fabsf(x[i * inc]);", "const float a = x[i * inc];"),
+    # iamax ignoring the increment
+    "iamax_unit_stride": ("const double a = fabs(x[i * inc]);", "const double a = fabs(x[i]);"),
 }
 
 

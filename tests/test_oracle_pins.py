@@ -15,7 +15,10 @@ Pins used (none retypes the oracle's own loops):
 - exact rational arithmetic (``fractions.Fraction``) and ``math.fsum`` for the
   reductions, within the Dot2 error bound of Ogita, Rump and Oishi (2005);
 - torch / numpy conversions to bfloat16 / binary16 and hand-worked rounding
-  cases for the 16-bit storage formats.
+  cases for the 16-bit storage formats;
+- numpy slicing for BLAS strided vectors (x[::inc], reversed for inc < 0),
+  numpy ``argmax`` (first occurrence) and hand-worked NaN / tie cases for
+  iamax, and ``math.fsum`` for asum.
 """
 from __future__ import annotations
 
@@ -337,6 +340,118 @@ def check_naive_f32(o):
 # the tests
 # --------------------------------------------------------------------------
 
+def check_blas_strides(o):
+    """Strided vectors against numpy slicing: inc > 0 takes x[0], x[inc], ...;
+    inc < 0 takes the same positions in reverse (reference BLAS); inc = 0
+    repeats x[0]."""
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal(40)
+    for n in (0, 1, 5, 13):
+        for inc in (1, 2, 3, -1, -2, -3):
+            span = o.blas_span(n, inc)
+            want = x[:span:abs(inc)] if inc > 0 else x[:span:abs(inc)][::-1]
+            got = o.gather(n, x, inc)
+            assert got.shape == (n,) and np.array_equal(got, want[:n]), (n, inc)
+    assert np.array_equal(o.gather(4, x, 0), np.full(4, x[0]))
+    # scatter: the strided slots of y take v, every other element is kept
+    y = rng.standard_normal(30)
+    v = rng.standard_normal(7)
+    for inc in (2, -3, 4):
+        want = y.copy()
+        sl = slice(0, o.blas_span(7, inc), abs(inc))
+        want[sl] = v if inc > 0 else v[::-1]
+        assert np.array_equal(o.scatter(7, v, y, inc), want), inc
+    # copy between two different strides: byte exact, 16-bit patterns too
+    h = rng.integers(0, 1 << 16, 50).astype(np.uint16)
+    out = o.copy(6, h, -4, np.zeros(20, np.uint16), 3)
+    want = np.zeros(20, np.uint16)
+    want[0:16:3] = h[0:21:4][::-1]
+    assert np.array_equal(out, want)
+
+
+def check_scal_axpy_strided(o):
+    """scal and strided axpy as numpy expressions on slices (binary64 and
+    binary32; numpy does not contract), torch for bfloat16 rounding."""
+    import torch
+
+    rng = np.random.default_rng(43)
+    x = rng.uniform(-2, 2, 64)
+    y = rng.uniform(-2, 2, 64)
+    alpha = 0.1  # not representable: binary32 must round it once
+    for inc in (1, 3, 5):
+        n = 12
+        sl = slice(0, o.blas_span(n, inc), abs(inc))
+        want = x.copy()
+        want[sl] = alpha * x[sl]
+        assert np.array_equal(bits64(o.scal(n, alpha, x, inc, "f64")), bits64(want)), inc
+        x32 = x.astype(np.float32)
+        want32 = x32.copy()
+        want32[sl] = np.float32(alpha) * x32[sl]
+        assert np.array_equal(bits32(o.scal(n, alpha, x32, inc, "f32")), bits32(want32)), inc
+    # inc <= 0 leaves x unchanged (reference BLAS)
+    assert np.array_equal(o.scal(5, 3.0, x, -1, "f64"), x)
+    # bfloat16: binary32 product, one round-to-nearest-even (torch's conversion)
+    hb = o.narrow(rng.uniform(-2, 2, 40).astype(np.float32), "bf16")
+    got = o.scal(10, alpha, hb, 4, "bf16")
+    wide = torch.from_numpy(o.widen(hb, "bf16").astype(np.float32))
+    prod = (wide[0:37:4] * torch.tensor(np.float32(alpha))).to(torch.bfloat16).view(torch.int16).numpy()
+    want = hb.copy()
+    want[0:37:4] = prod.view(np.uint16)
+    assert np.array_equal(got, want)
+    # strided axpy, x and y with different increments (one negative)
+    n, incx, incy = 9, -2, 3
+    xs = x[:o.blas_span(n, incx):2][::-1]
+    want = y.copy()
+    want[0:o.blas_span(n, incy):3] = alpha * xs + y[0:o.blas_span(n, incy):3]
+    assert np.array_equal(bits64(o.axpy_strided(n, alpha, x, incx, y, incy, "f64")), bits64(want))
+    x32, y32 = x.astype(np.float32), y.astype(np.float32)
+    want32 = y32.copy()
+    want32[0:o.blas_span(n, incy):3] = np.float32(alpha) * x32[:o.blas_span(n, incx):2][::-1] + \
+        y32[0:o.blas_span(n, incy):3]
+    assert np.array_equal(bits32(o.axpy_strided(n, alpha, x32, incx, y32, incy, "f32")), bits32(want32))
+
+
+def check_asum(o):
+    """asum: integers sum exactly; random values against math.fsum of |x|
+    (correctly rounded) within the Dot2 bound."""
+    v = np.array([3.0, -4.0, 0.0, -1.0, 2.0])
+    assert o.asum(v)[0] == 10.0
+    rng = np.random.default_rng(47)
+    for n in (1, 17, 1000):
+        x = rng.standard_normal(n) * np.exp(rng.uniform(-20, 20, n))
+        exact = math.fsum(abs(float(t)) for t in x)
+        got = o.asum(x)[0]
+        assert abs(got - exact) <= dot2_bound(n, exact, exact), (n, got, exact)
+
+
+def check_iamax(o):
+    """iamax against numpy argmax of |x| (first occurrence of the maximum) and
+    hand-worked cases: ties, NaNs, strides, empty vectors."""
+    rng = np.random.default_rng(53)
+    for dtype in ("f64", "f32"):
+        for n in (1, 2, 33, 500):
+            x = rng.standard_normal(3 * n)
+            if dtype == "f32":
+                x = x.astype(np.float32)
+            for inc in (1, 3):
+                want = int(np.argmax(np.abs(x[:o.blas_span(n, inc):inc])))
+                assert o.iamax(n, x, inc, dtype) == want, (dtype, n, inc)
+    t = np.array([1.0, -3.0, 3.0, 2.0, -3.0])
+    assert o.iamax(5, t, 1, "f64") == 1                       # ties: the first
+    assert o.iamax(3, t, 2, "f64") == 1                       # elements 1, 3, 3
+    nan = float("nan")
+    assert o.iamax(4, np.array([1.0, nan, 5.0, -5.0]), 1, "f64") == 2   # a NaN is skipped
+    assert o.iamax(3, np.array([nan, 9.0, 1.0]), 1, "f64") == 0          # NaN first: kept
+    assert o.iamax(3, np.array([0.0, -0.0, 0.0]), 1, "f64") == 0
+    assert o.iamax(0, t, 1, "f64") == -1 and o.iamax(3, t, 0, "f64") == -1
+    assert o.iamax(3, t, -1, "f64") == -1
+    # 16-bit storage compares exact values: bfloat16 3.0 vs its neighbour 3.015625
+    hb = o.narrow(np.array([3.0, -3.015625, 3.0], np.float32), "bf16")
+    assert o.iamax(3, hb, 1, "bf16") == 1
+    hf = o.narrow(np.array([1.0, 65504.0, -65504.0], np.float32), "f16")
+    assert o.iamax(3, hf, 1, "f16") == 1
+
+
 CHECKS = {
     "fig1_golden": check_fig1_golden,
     "python_float_trees_f64": check_python_float_trees_f64,
@@ -357,6 +472,10 @@ CHECKS = {
     "dot_fsum": check_dot_fsum,
     "nrm2": check_nrm2,
     "naive_f32": check_naive_f32,
+    "blas_strides": check_blas_strides,
+    "scal_axpy_strided": check_scal_axpy_strided,
+    "asum": check_asum,
+    "iamax": check_iamax,
 }
 
 
