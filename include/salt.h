@@ -143,6 +143,54 @@ salt_status salt_nrm2_expr(const uint32_t *prog, int32_t prog_len,
                            void *result, void *workspace, size_t ws_bytes,
                            salt_dtype dtype, void *hip_stream);
 
+/* ---- BLAS level-1 with increments ------------------------------------------
+ * The BLAS interface the paper measures against (Sec. 1; Sec. 5, xDOT,
+ * xSCAL, xAXPY, xCOPY). A vector argument is (pointer, n, inc): element i
+ * sits at x[i*inc] for inc >= 0 and at x[(n-1-i)*|inc|] for inc < 0, so the
+ * pointer is always the lowest address and the vector spans
+ * 1 + (n-1)*|inc| elements; inc = 0 repeats x[0] (inputs only). All
+ * pointers are device pointers. Unit increments run the contiguous kernels
+ * above (same bits); other increments run element-strided kernels with the
+ * same arithmetic, so a strided call gives the bits the contiguous call
+ * gives on the gathered vectors. The routines of one vector (scal, nrm2,
+ * asum, iamax) treat inc <= 0 as the reference BLAS does: nothing is done,
+ * or the result is 0 (nrm2, asum) or -1 (iamax). Errors (SALT_ERR_ARG): n < 0,
+ * a NULL pointer with n > 0, a span past 2^59 elements, an output increment
+ * of 0 with n > 1 (every element would land on one address). An output must
+ * not overlap an input except as the very same vector (same pointer and
+ * increment); this is not checked. Reductions take the workspace of
+ * salt_reduce_workspace_bytes(n, dtype) and write the result type of
+ * salt_dot. */
+
+/* x_i <- alpha*x_i, alpha rounded once to the compute type. */
+salt_status salt_scal(int64_t n, double alpha, void *x, int64_t incx,
+                      salt_dtype dtype, void *hip_stream);
+
+/* y_i <- x_i (bit copy). */
+salt_status salt_copy(int64_t n, const void *x, int64_t incx, void *y, int64_t incy,
+                      salt_dtype dtype, void *hip_stream);
+
+/* y_i <- fl(fl(alpha*x_i) + y_i), as salt_axpy. */
+salt_status salt_axpy_strided(int64_t n, double alpha, const void *x, int64_t incx,
+                              void *y, int64_t incy, salt_dtype dtype, void *hip_stream);
+
+/* sum_i x_i*y_i, sqrt(sum_i x_i^2) and sum_i |x_i|, with salt_dot's
+ * summation order over the element index i and its accumulators. */
+salt_status salt_dot_strided(int64_t n, const void *x, int64_t incx, const void *y, int64_t incy,
+                             void *result, void *workspace, size_t ws_bytes,
+                             salt_dtype dtype, void *hip_stream);
+salt_status salt_nrm2_strided(int64_t n, const void *x, int64_t incx, void *result,
+                              void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream);
+salt_status salt_asum(int64_t n, const void *x, int64_t incx, void *result,
+                      void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream);
+
+/* Index (from 0) of the first element of largest magnitude, written to
+ * *result (device int64). As in the reference BLAS scan, a NaN is never
+ * chosen unless it is element 0 (then the answer is 0); -1 for n < 1 or
+ * incx <= 0. The answer is unique, so it does not depend on the launch. */
+salt_status salt_iamax(int64_t n, const void *x, int64_t incx, int64_t *result,
+                       void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream);
+
 /* ---- launch control (autotuning and introspection) ------------------------
  * The paper picks the number of instruction packages per loop by trial
  * (Sec. 4.3); here the equivalent knobs are chosen per tree, element type

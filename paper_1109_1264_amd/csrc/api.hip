@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "blas1.hpp"
 #include "expr.hpp"
 #include "launch.hpp"
 #include "program.hpp"
@@ -252,9 +253,12 @@ salt_status eval_impl(const uint32_t *prog, int32_t prog_len, const void *const 
     return device_status(launch_interp(L, p, dtype));
 }
 
+// dot (mode kModeDot) reads x and y; nrm2 and asum read x only and share
+// nrm2's tuning (the same traffic).
 salt_status reduce_impl(int64_t n, const void *x, const void *y, void *result, void *ws,
                         size_t ws_bytes, int dtype, void *stream, const salt_launch_config *cfg,
-                        bool nrm2) {
+                        int mode) {
+    const bool nrm2 = mode != kModeDot;  // one operand
     if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
     if (n < 0) return fail(SALT_ERR_ARG, "negative length");
     if ((uint64_t)n > (uint64_t)INT64_MAX / 16) return fail(SALT_ERR_ARG, "length too large");
@@ -284,12 +288,75 @@ salt_status reduce_impl(int64_t n, const void *x, const void *y, void *result, v
     L.unroll = c.unroll;
     L.nontemporal = c.nontemporal;
     L.blocks = c.blocks;
-    L.nrm2 = nrm2 ? 1 : 0;
+    L.mode = mode;
     L.stream = stream;
     return device_status(launch_reduce(L, dtype));
 }
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---- BLAS level-1 with increments -----------------------------------------
+constexpr int64_t kMaxSpan = (int64_t)1 << 59;  // elements one strided vector may span
+
+uint64_t abs_inc(int64_t inc) { return inc < 0 ? (uint64_t)(-(inc + 1)) + 1u : (uint64_t)inc; }
+
+// Bytes from the vector's pointer to the end of its last element.
+size_t span_bytes(int64_t n, int64_t inc, int dtype) {
+    return n <= 0 ? 0 : (size_t)(1 + (uint64_t)(n - 1) * abs_inc(inc)) * esize(dtype);
+}
+
+salt_status check_vec(int64_t n, const void *p, int64_t inc, const char *name, bool output) {
+    if (n <= 0) return SALT_OK;
+    if (!p) return fail(SALT_ERR_ARG, std::string(name) + " is NULL");
+    if (n > 1 && abs_inc(inc) > (uint64_t)(kMaxSpan - 1) / (uint64_t)(n - 1))
+        return fail(SALT_ERR_ARG, std::string(name) + ": the strided vector spans more than 2^59 elements");
+    if (output && inc == 0 && n > 1)
+        return fail(SALT_ERR_ARG, std::string(name) + ": output increment 0 would write one element n times");
+    return SALT_OK;
+}
+
+salt_status check_reduce_ws(int64_t n, int dtype, void *ws, size_t ws_bytes, const void *x, size_t xb,
+                            const void *y, size_t yb) {
+    const size_t need = salt_reduce_workspace_bytes(n, (salt_dtype)dtype);
+    if (need == 0) return SALT_OK;
+    if (!ws) return fail(SALT_ERR_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 7u) != 0) return fail(SALT_ERR_WORKSPACE, "workspace not 8-byte aligned");
+    if (ws_bytes < need)
+        return fail(SALT_ERR_WORKSPACE,
+                    "workspace has " + std::to_string(ws_bytes) + " bytes, needs " + std::to_string(need));
+    if (any_overlap(ws, need, x, xb) || (y && any_overlap(ws, need, y, yb)))
+        return fail(SALT_ERR_WORKSPACE, "workspace overlaps an input");
+    return SALT_OK;
+}
+
+// dot (both vectors), nrm2 / asum (x only; inc <= 0 gives 0 as in BLAS).
+salt_status strided_reduce_impl(int64_t n, const void *x, int64_t incx, const void *y, int64_t incy,
+                                void *result, void *ws, size_t ws_bytes, int dtype, void *stream, int mode) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    if (!result) return fail(SALT_ERR_ARG, "result pointer is NULL");
+    const bool dot = mode == kModeDot;
+    if (!dot && incx <= 0) n = 0;
+    salt_status s = check_vec(n, x, incx, "x", false);
+    if (s == SALT_OK && dot) s = check_vec(n, y, incy, "y", false);
+    if (s != SALT_OK) return s;
+    if (n == 0 || (incx == 1 && (!dot || incy == 1)))
+        return reduce_impl(n, x, dot ? y : x, result, ws, ws_bytes, dtype, stream, nullptr, mode);
+    s = check_reduce_ws(n, dtype, ws, ws_bytes, x, span_bytes(n, incx, dtype), dot ? y : nullptr,
+                        dot ? span_bytes(n, incy, dtype) : 0);
+    if (s != SALT_OK) return s;
+    StridedReduceLaunch L;
+    L.x = x;
+    L.incx = incx;
+    L.y = dot ? y : x;
+    L.incy = dot ? incy : incx;
+    L.result = result;
+    L.ws = (double *)ws;
+    L.n = n;
+    L.mode = mode;
+    L.stream = stream;
+    return device_status(launch_strided_reduce(L, dtype));
+}
 
 }  // namespace
 }  // namespace salt
@@ -449,22 +516,96 @@ int64_t salt_reduce_tile_elems(salt_dtype dtype) { return reduce_tile_elems(dtyp
 
 salt_status salt_dot(int64_t n, const void *x, const void *y, void *result, void *workspace,
                      size_t ws_bytes, salt_dtype dtype, void *hip_stream) {
-    return reduce_impl(n, x, y, result, workspace, ws_bytes, dtype, hip_stream, nullptr, false);
+    return reduce_impl(n, x, y, result, workspace, ws_bytes, dtype, hip_stream, nullptr, kModeDot);
 }
 
 salt_status salt_dot_ex(int64_t n, const void *x, const void *y, void *result, void *workspace,
                         size_t ws_bytes, salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
-    return reduce_impl(n, x, y, result, workspace, ws_bytes, dtype, hip_stream, cfg, false);
+    return reduce_impl(n, x, y, result, workspace, ws_bytes, dtype, hip_stream, cfg, kModeDot);
+}
+
+salt_status salt_scal(int64_t n, double alpha, void *x, int64_t incx, salt_dtype dtype, void *hip_stream) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    if (n == 0 || incx <= 0) return SALT_OK;  // reference BLAS: nothing to do
+    salt_status s = check_vec(n, x, incx, "x", true);
+    if (s != SALT_OK) return s;
+    if (incx == 1) {
+        static const uint32_t prog[3] = {SALT_TOKEN(SALT_OP_SCALAR, 0), SALT_TOKEN(SALT_OP_LOAD, 0),
+                                         SALT_TOKEN(SALT_OP_MUL, 0)};
+        const void *ops[1] = {x};
+        return eval_impl(prog, 3, ops, 1, &alpha, 1, x, n, dtype, hip_stream, nullptr);
+    }
+    StridedMapLaunch L{x, incx, x, incx, n, alpha, kMapScal, hip_stream};
+    return device_status(launch_strided_map(L, dtype));
+}
+
+salt_status salt_copy(int64_t n, const void *x, int64_t incx, void *y, int64_t incy, salt_dtype dtype,
+                      void *hip_stream) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    salt_status s = check_vec(n, x, incx, "x", false);
+    if (s == SALT_OK) s = check_vec(n, y, incy, "y", true);
+    if (s != SALT_OK || n == 0) return s;
+    if (incx == 1 && incy == 1) {
+        static const uint32_t prog[1] = {SALT_TOKEN(SALT_OP_LOAD, 0)};
+        const void *ops[1] = {x};
+        return eval_impl(prog, 1, ops, 1, nullptr, 0, y, n, dtype, hip_stream, nullptr);
+    }
+    StridedMapLaunch L{x, incx, y, incy, n, 0.0, kMapCopy, hip_stream};
+    return device_status(launch_strided_map(L, dtype));
+}
+
+salt_status salt_axpy_strided(int64_t n, double alpha, const void *x, int64_t incx, void *y, int64_t incy,
+                              salt_dtype dtype, void *hip_stream) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    salt_status s = check_vec(n, x, incx, "x", false);
+    if (s == SALT_OK) s = check_vec(n, y, incy, "y", true);
+    if (s != SALT_OK || n == 0) return s;
+    if (incx == 1 && incy == 1) return salt_axpy(n, alpha, x, y, dtype, hip_stream);
+    StridedMapLaunch L{x, incx, y, incy, n, alpha, kMapAxpy, hip_stream};
+    return device_status(launch_strided_map(L, dtype));
+}
+
+salt_status salt_dot_strided(int64_t n, const void *x, int64_t incx, const void *y, int64_t incy, void *result,
+                             void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream) {
+    return strided_reduce_impl(n, x, incx, y, incy, result, workspace, ws_bytes, dtype, hip_stream, kModeDot);
+}
+
+salt_status salt_nrm2_strided(int64_t n, const void *x, int64_t incx, void *result, void *workspace,
+                              size_t ws_bytes, salt_dtype dtype, void *hip_stream) {
+    return strided_reduce_impl(n, x, incx, x, incx, result, workspace, ws_bytes, dtype, hip_stream, kModeNrm2);
+}
+
+salt_status salt_asum(int64_t n, const void *x, int64_t incx, void *result, void *workspace, size_t ws_bytes,
+                      salt_dtype dtype, void *hip_stream) {
+    return strided_reduce_impl(n, x, incx, x, incx, result, workspace, ws_bytes, dtype, hip_stream, kModeAsum);
+}
+
+salt_status salt_iamax(int64_t n, const void *x, int64_t incx, int64_t *result, void *workspace,
+                       size_t ws_bytes, salt_dtype dtype, void *hip_stream) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string(dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    if (!result) return fail(SALT_ERR_ARG, "result pointer is NULL");
+    if (incx <= 0) n = 0;  // the answer is -1
+    salt_status s = check_vec(n, x, incx, "x", false);
+    if (s == SALT_OK)
+        s = check_reduce_ws(n, dtype, workspace, ws_bytes, x, span_bytes(n, incx, dtype), nullptr, 0);
+    if (s != SALT_OK) return s;
+    if (((uintptr_t)result & 7u) != 0) return fail(SALT_ERR_ARG, "result not 8-byte aligned");
+    IamaxLaunch L{x, incx, result, (int64_t *)workspace, n, incx == 1 && aligned16(x) ? 1 : 0, hip_stream};
+    return device_status(launch_iamax(L, dtype));
 }
 
 salt_status salt_nrm2(int64_t n, const void *x, void *result, void *workspace, size_t ws_bytes,
                       salt_dtype dtype, void *hip_stream) {
-    return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, nullptr, true);
+    return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, nullptr, kModeNrm2);
 }
 
 salt_status salt_nrm2_ex(int64_t n, const void *x, void *result, void *workspace, size_t ws_bytes,
                          salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
-    return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, cfg, true);
+    return reduce_impl(n, x, x, result, workspace, ws_bytes, dtype, hip_stream, cfg, kModeNrm2);
 }
 
 salt_status salt_dot_expr(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,

@@ -34,10 +34,12 @@ int catalogue_program(int id, uint32_t *tokens, int cap, const char **name);
 // Generic interpreter launch for a compiled program.
 hipError_t launch_interp(const EvalLaunch &L, const Program &p, int dtype);
 
-// Reductions (reduce.hip).
+// Reductions (reduce.hip): what each element contributes.
+enum ReduceMode { kModeDot = 0, kModeNrm2 = 1, kModeAsum = 2 };
+
 struct ReduceLaunch {
     const void *x;
-    const void *y;  // == x for nrm2
+    const void *y;  // == x for nrm2 and asum
     void *result;
     double *ws;     // one binary64 partial per tile
     int64_t n;
@@ -45,7 +47,7 @@ struct ReduceLaunch {
     int32_t unroll;     // chunks per lane per load burst
     int32_t nontemporal;
     int64_t blocks;     // 0 = one workgroup per tile, else grid size
-    int32_t nrm2;
+    int32_t mode;       // ReduceMode
     void *stream;
 };
 int64_t reduce_tile_elems(int dtype);

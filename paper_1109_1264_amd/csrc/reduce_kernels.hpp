@@ -1,5 +1,6 @@
 // reduce_kernels.hpp -- dot and nrm2 (the reductions at the root of an expression
-// tree, Sec. 2; the node's reduction step, Sec. 4.2) for gfx950.
+// tree, Sec. 2; the node's reduction step, Sec. 4.2), and asum (the BLAS
+// level-1 sum of magnitudes) for gfx950.
 //
 // Deterministic two-pass scheme; the summation order (reduce_common.hpp)
 // depends only on n and the element type:
@@ -28,8 +29,19 @@ struct RedArgs {
     int32_t vec;
 };
 
-template <int DT, int UR, bool NT, bool NRM>
+// The value a reduction adds for element (x, y): x*y (dot), x*x (nrm2), or
+// |x|*1 (asum; the product is exact, so the accumulators add |x| itself).
+template <int DT, int MODE>
+__device__ __forceinline__ void acc_add(Acc<DT> &acc, typename Tr<DT>::C x, typename Tr<DT>::C y) {
+    using C = typename Tr<DT>::C;
+    if constexpr (MODE == kModeDot) acc.add(x, y);
+    else if constexpr (MODE == kModeNrm2) acc.add(x, x);
+    else acc.add(x < (C)0 ? -x : x, (C)1);
+}
+
+template <int DT, int UR, bool NT, int MODE>
 __global__ __launch_bounds__(kBlock) void k_reduce_pass1(RedArgs a) {
+    constexpr bool NRM = MODE != kModeDot;  // one operand
     constexpr int V = Tr<DT>::V;
     constexpr int64_t T = tile_elems<DT>();
     const int64_t n_tiles = (a.n + T - 1) / T;
@@ -63,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pass1(RedArgs a) {
 #pragma unroll
                 for (int p = 0; p < V; ++p) {
                     const auto xv = Tr<DT>::get(xr[u], p);
-                    acc[p].add(xv, NRM ? xv : Tr<DT>::get(yr[u], p));
+                    acc_add<DT, MODE>(acc[p], xv, NRM ? xv : Tr<DT>::get(yr[u], p));
                 }
         }
         const double v = block_sum<kBlock / 64>(lane_value<DT>(acc), lds);
@@ -158,21 +170,21 @@ __global__ __launch_bounds__(kFinalBlock) void k_reduce_pass2(const double *ws, 
     if (threadIdx.x == 0) store_result<DT, NRM>(result, r);
 }
 
-template <int DT, int UR, bool NT, bool NRM>
+template <int DT, int UR, bool NT, int MODE>
 static void launch_pass1(const ReduceLaunch &L, int64_t grid) {
     RedArgs a{L.x, L.y, L.ws, L.n, L.vec};
-    hipLaunchKernelGGL((k_reduce_pass1<DT, UR, NT, NRM>), dim3((unsigned)grid), dim3(kBlock), 0,
+    hipLaunchKernelGGL((k_reduce_pass1<DT, UR, NT, MODE>), dim3((unsigned)grid), dim3(kBlock), 0,
                        (hipStream_t)L.stream, a);
 }
 
-template <int DT, bool NRM>
+template <int DT, int MODE>
 static void pass1_dispatch(const ReduceLaunch &L, int64_t grid) {
     const bool nt = L.nontemporal != 0;
     switch (L.unroll) {
-        case 4: nt ? launch_pass1<DT, 4, true, NRM>(L, grid) : launch_pass1<DT, 4, false, NRM>(L, grid); break;
-        case 8: nt ? launch_pass1<DT, 8, true, NRM>(L, grid) : launch_pass1<DT, 8, false, NRM>(L, grid); break;
-        case 16: nt ? launch_pass1<DT, 16, true, NRM>(L, grid) : launch_pass1<DT, 16, false, NRM>(L, grid); break;
-        default: nt ? launch_pass1<DT, 2, true, NRM>(L, grid) : launch_pass1<DT, 2, false, NRM>(L, grid); break;
+        case 4: nt ? launch_pass1<DT, 4, true, MODE>(L, grid) : launch_pass1<DT, 4, false, MODE>(L, grid); break;
+        case 8: nt ? launch_pass1<DT, 8, true, MODE>(L, grid) : launch_pass1<DT, 8, false, MODE>(L, grid); break;
+        case 16: nt ? launch_pass1<DT, 16, true, MODE>(L, grid) : launch_pass1<DT, 16, false, MODE>(L, grid); break;
+        default: nt ? launch_pass1<DT, 2, true, MODE>(L, grid) : launch_pass1<DT, 2, false, MODE>(L, grid); break;
     }
 }
 
@@ -183,12 +195,13 @@ static hipError_t launch_reduce_dt(const ReduceLaunch &L) {
     if (n_tiles > 0) {
         int64_t grid = L.blocks > 0 && L.blocks < n_tiles ? L.blocks : n_tiles;
         if (grid > 0x7fffffff) grid = 0x7fffffff;
-        if (L.nrm2) pass1_dispatch<DT, true>(L, grid);
-        else pass1_dispatch<DT, false>(L, grid);
+        if (L.mode == kModeNrm2) pass1_dispatch<DT, kModeNrm2>(L, grid);
+        else if (L.mode == kModeAsum) pass1_dispatch<DT, kModeAsum>(L, grid);
+        else pass1_dispatch<DT, kModeDot>(L, grid);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (L.nrm2)
+    if (L.mode == kModeNrm2)
         hipLaunchKernelGGL((k_reduce_pass2<DT, true>), dim3(1), dim3(kFinalBlock), 0, (hipStream_t)L.stream,
                            (const double *)L.ws, n_tiles, L.result);
     else
@@ -204,7 +217,7 @@ static hipError_t launch_reduce_dt(const ReduceLaunch &L) {
 static uint8_t shift_slot(uint8_t c) { return (uint8_t)(c + 1); }
 
 // P's codes, then Q's shifted by one slot (nullptr Q: P alone).
-static void fill_pair(InterpProg2 &g, const Program &px, const Program *py) {
+static inline void fill_pair(InterpProg2 &g, const Program &px, const Program *py) {
     g.clear();
     int len = 0;
     for (int t = 0; t < px.len; ++t, ++len) g.set(len, px.code_raw[t], px.sarg_raw[t]);

@@ -83,6 +83,13 @@ def lib() -> ctypes.CDLL:
         "salt_dot_ex": ([I64, P, P, P, P, SZ, I32, P, CFG], I32),
         "salt_nrm2": ([I64, P, P, P, SZ, I32, P], I32),
         "salt_nrm2_ex": ([I64, P, P, P, SZ, I32, P, CFG], I32),
+        "salt_scal": ([I64, D, P, I64, I32, P], I32),
+        "salt_copy": ([I64, P, I64, P, I64, I32, P], I32),
+        "salt_axpy_strided": ([I64, D, P, I64, P, I64, I32, P], I32),
+        "salt_dot_strided": ([I64, P, I64, P, I64, P, P, SZ, I32, P], I32),
+        "salt_nrm2_strided": ([I64, P, I64, P, P, SZ, I32, P], I32),
+        "salt_asum": ([I64, P, I64, P, P, SZ, I32, P], I32),
+        "salt_iamax": ([I64, P, I64, P, P, SZ, I32, P], I32),
         "salt_tuning_load": ([ctypes.c_char_p], I32),
         "salt_tuning_lookup": ([I32, I32, I32, I64, CFG], I32),
         "salt_catalogue_count": ([], I32),
@@ -272,6 +279,98 @@ def salt_nrm2(x, n: int | None = None, result=None, ws=None, stream=None, config
     else:
         st = L.salt_nrm2_ex(n, _dev(x), _dev(result), _dev(ws), nb, d, _stream_ptr(stream), _cfg(config))
     check(st)
+    return result
+
+
+# ---------------------------------------------------------------------------
+# BLAS level-1 with increments: a vector is (tensor, n, inc), element i at
+# t[i*inc] (inc >= 0) or t[(n-1-i)*|inc|] (inc < 0); the tensor holds at
+# least 1 + (n-1)*|inc| elements.
+# ---------------------------------------------------------------------------
+
+def _span(n: int, inc: int) -> int:
+    return 0 if n <= 0 else 1 + (n - 1) * abs(inc)
+
+
+def _strided(t, n: int, inc: int, name: str, needed: bool = True):
+    if needed and n > 0 and t.numel() < _span(n, inc):
+        raise ValueError("%s holds %d elements, the strided vector spans %d" % (name, t.numel(), _span(n, inc)))
+    return _dev(t)
+
+
+def salt_scal(alpha: float, x, n: int, incx: int = 1, stream=None) -> None:
+    """x_i <- alpha*x_i (nothing for incx <= 0)."""
+    check(lib().salt_scal(n, float(alpha), _strided(x, n, incx, "x", incx > 0), incx, dtype_code(x),
+                          _stream_ptr(stream)))
+
+
+def salt_copy(x, y, n: int, incx: int = 1, incy: int = 1, stream=None) -> None:
+    """y_i <- x_i."""
+    d = dtype_code(y)
+    if dtype_code(x) != d:
+        raise TypeError("x and y must share a dtype")
+    check(lib().salt_copy(n, _strided(x, n, incx, "x"), incx, _strided(y, n, incy, "y"), incy, d,
+                          _stream_ptr(stream)))
+
+
+def salt_axpy_strided(alpha: float, x, y, n: int, incx: int = 1, incy: int = 1, stream=None) -> None:
+    """y_i <- alpha*x_i + y_i."""
+    d = dtype_code(y)
+    if dtype_code(x) != d:
+        raise TypeError("x and y must share a dtype")
+    check(lib().salt_axpy_strided(n, float(alpha), _strided(x, n, incx, "x"), incx, _strided(y, n, incy, "y"),
+                                  incy, d, _stream_ptr(stream)))
+
+
+def _reduce_args(x, n, result, ws):
+    d = dtype_code(x)
+    result = _result_tensor(d, x.device) if result is None else result
+    ws = workspace(n, d, x.device) if ws is None else ws
+    return d, result, ws, ws.numel() * ws.element_size()
+
+
+def salt_dot_strided(x, y, n: int, incx: int = 1, incy: int = 1, result=None, ws=None, stream=None):
+    """Device scalar sum_i x_i*y_i over strided vectors."""
+    if dtype_code(y) != dtype_code(x):
+        raise TypeError("x and y must share a dtype")
+    d, result, ws, nb = _reduce_args(x, n, result, ws)
+    check(lib().salt_dot_strided(n, _strided(x, n, incx, "x"), incx, _strided(y, n, incy, "y"), incy,
+                                 _dev(result), _dev(ws), nb, d, _stream_ptr(stream)))
+    return result
+
+
+def salt_nrm2_strided(x, n: int, incx: int = 1, result=None, ws=None, stream=None):
+    """Device scalar sqrt(sum_i x_i^2) (0 for incx <= 0)."""
+    d, result, ws, nb = _reduce_args(x, n, result, ws)
+    check(lib().salt_nrm2_strided(n, _strided(x, n, incx, "x", incx > 0), incx, _dev(result), _dev(ws), nb, d,
+                                  _stream_ptr(stream)))
+    return result
+
+
+def salt_asum(x, n: int | None = None, incx: int = 1, result=None, ws=None, stream=None):
+    """Device scalar sum_i |x_i| (0 for incx <= 0)."""
+    if n is None:
+        n = x.numel()
+    d, result, ws, nb = _reduce_args(x, n, result, ws)
+    check(lib().salt_asum(n, _strided(x, n, incx, "x", incx > 0), incx, _dev(result), _dev(ws), nb, d,
+                          _stream_ptr(stream)))
+    return result
+
+
+def salt_iamax(x, n: int | None = None, incx: int = 1, result=None, ws=None, stream=None):
+    """Device int64: index (from 0) of the first element of largest magnitude;
+    -1 for n < 1 or incx <= 0."""
+    import torch
+
+    if n is None:
+        n = x.numel()
+    d = dtype_code(x)
+    result = torch.empty(1, dtype=torch.int64, device=x.device) if result is None else result
+    if result.dtype != torch.int64:
+        raise TypeError("result must be an int64 tensor")
+    ws = workspace(n, d, x.device) if ws is None else ws
+    check(lib().salt_iamax(n, _strided(x, n, incx, "x", incx > 0), incx, _dev(result), _dev(ws),
+                           ws.numel() * ws.element_size(), d, _stream_ptr(stream)))
     return result
 
 

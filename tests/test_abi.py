@@ -229,3 +229,44 @@ def test_reduce_expr_argument_errors(L):
     assert L.salt_nrm2_expr(px, 1, ops, 2, sc, 0, n, R, X + 8, need, S.F64, None) == S.ERR_WORKSPACE
     deep = (ctypes.c_uint32 * 15)(*([T(S.LOAD, 0)] * 8 + [T(S.SUB)] * 7))
     assert f(deep, 15, deep, 15, ops, 2, sc, 0, n, R, W, need, S.F64, None) == S.ERR_UNSUPPORTED
+
+
+def test_blas1_strided_argument_errors(L):
+    """Strided BLAS level-1: rejected arguments, and the calls that do nothing
+    (n = 0, or inc <= 0 for scal) return OK without touching the device."""
+    X, Y, R, W = 0x1000000, 0x2000000, 0x3000000, 0x4000000
+    F64, F32 = S.F64, S.F32
+    # scal
+    assert L.salt_scal(-1, 2.0, X, 1, F64, None) == S.ERR_ARG
+    assert L.salt_scal(5, 2.0, None, 2, F64, None) == S.ERR_ARG
+    assert L.salt_scal(5, 2.0, X, 2, 9, None) == S.ERR_ARG
+    assert L.salt_scal(1 << 40, 2.0, X, 1 << 20, F64, None) == S.ERR_ARG      # span past 2^59
+    assert L.salt_scal(5, 2.0, X, 0, F64, None) == S.OK                       # reference BLAS: no-op
+    assert L.salt_scal(5, 2.0, X, -3, F64, None) == S.OK
+    assert L.salt_scal(0, 2.0, None, 1, F64, None) == S.OK
+    # copy / axpy: an output increment of 0 with n > 1 is rejected
+    assert L.salt_copy(3, X, 1, Y, 0, F32, None) == S.ERR_ARG
+    assert L.salt_copy(3, None, 2, Y, 1, F32, None) == S.ERR_ARG
+    assert L.salt_copy(-2, X, 1, Y, 1, F32, None) == S.ERR_ARG
+    assert L.salt_copy(0, None, 1, None, 1, F32, None) == S.OK
+    assert L.salt_axpy_strided(3, 1.0, X, 0, Y, 0, F64, None) == S.ERR_ARG
+    assert L.salt_axpy_strided(3, 1.0, X, 2, None, 1, F64, None) == S.ERR_ARG
+    assert L.salt_axpy_strided(1 << 50, 1.0, X, 1, Y, -(1 << 12), F64, None) == S.ERR_ARG
+    # strided reductions: result, workspace size, alignment and overlap
+    n, inc = 100000, 3
+    need = S.salt_reduce_workspace_bytes(n, F64)
+    assert L.salt_dot_strided(n, X, inc, Y, 2, None, W, need, F64, None) == S.ERR_ARG
+    assert L.salt_dot_strided(n, X, inc, Y, 2, R, None, need, F64, None) == S.ERR_WORKSPACE
+    assert L.salt_dot_strided(n, X, inc, Y, 2, R, W, need - 8, F64, None) == S.ERR_WORKSPACE
+    assert L.salt_dot_strided(n, X, -inc, Y, 2, R, W + 4, need, F64, None) == S.ERR_WORKSPACE
+    # the span of x with |inc| = 3 reaches X + 8*(1 + 3(n-1)); a workspace inside it
+    assert L.salt_dot_strided(n, X, -inc, Y, 2, R, X + 8 * 3 * (n - 10), need, F64, None) == S.ERR_WORKSPACE
+    assert L.salt_dot_strided(n, None, inc, Y, 2, R, W, need, F64, None) == S.ERR_ARG
+    assert L.salt_nrm2_strided(n, X, inc, R, W, need - 8, F64, None) == S.ERR_WORKSPACE
+    assert L.salt_asum(n, X, inc, R, W + 4, need, F64, None) == S.ERR_WORKSPACE
+    assert L.salt_asum(-1, X, inc, R, W, need, F64, None) == S.ERR_ARG
+    # iamax: int64 result, 8-byte aligned; workspace as the reductions
+    assert L.salt_iamax(n, X, inc, None, W, need, F64, None) == S.ERR_ARG
+    assert L.salt_iamax(n, X, inc, R + 4, W, need, F64, None) == S.ERR_ARG
+    assert L.salt_iamax(n, X, inc, R, W, need - 8, F64, None) == S.ERR_WORKSPACE
+    assert L.salt_iamax(n, None, inc, R, W, need, F64, None) == S.ERR_ARG

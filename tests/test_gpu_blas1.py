@@ -1,0 +1,249 @@
+"""Parity of the strided BLAS level-1 interface (scal, copy, strided axpy,
+strided dot / nrm2, asum, iamax) with the oracle.
+
+Element-wise routines are bit-exact against the oracle over the whole buffer
+(elements outside the strided vector must be untouched). Strided reductions
+must give the same bits as the contiguous reduction of the gathered vectors
+(same order, same accumulators) and lie within the stated tolerance of the
+oracle's Dot2 value. iamax is an index: exact."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1109_1264_amd import salt as S
+from paper_1109_1264_amd import workloads
+from tests.gpu_util import CODE, first_mismatch, oracle_bits, to_dev, to_host_bits
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["f64", "f32", "bf16", "f16"]
+
+
+def tile(dtype):
+    return S.salt_reduce_tile_elems(CODE[dtype])
+
+
+def host_vec(n, inc, dtype, seed):
+    """Seeded stored values, uniform on [-1, 1), for a buffer that holds an
+    n-element vector with increment inc (at least one element)."""
+    span = max(1, oracle.blas_span(n, inc))
+    (a,) = workloads.uniform(span, dtype, seed, 1)
+    return a
+
+
+def sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def scalar(t):
+    sync()
+    return float(t.item())
+
+
+# ---------------------------------------------------------------------------
+# element-wise
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_scal(dtype):
+    T = tile(dtype)
+    for k, (n, inc) in enumerate([(0, 1), (1, 1), (7, 2), (1000, 1), (1000, 5), (T + 3, 3), (100003, 2),
+                                  (9, 0), (9, -2)]):
+        x = host_vec(n, inc, dtype, 2000 + k)
+        print("scal", dtype, n, inc, flush=True)
+        d = to_dev(x, dtype)
+        S.salt_scal(0.1, d, n, inc)
+        got = to_host_bits(d, dtype)
+        want = oracle_bits(oracle.scal(n, 0.1, x, inc, dtype), dtype)
+        assert np.array_equal(got, want), (dtype, n, inc, first_mismatch(got, want))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_copy(dtype):
+    for k, (n, ix, iy) in enumerate([(0, 1, 1), (1, 1, 1), (5000, 1, 1), (5000, 2, 1), (5000, 1, 3),
+                                     (4099, -2, 3), (4099, 3, -1), (777, 0, 2), (1000, -1, -1)]):
+        x = host_vec(n, ix, dtype, 2100 + k)
+        y = host_vec(n, iy, dtype, 2200 + k)
+        print("copy", dtype, n, ix, iy, flush=True)
+        dy = to_dev(y, dtype)
+        S.salt_copy(to_dev(x, dtype), dy, n, ix, iy)
+        got = to_host_bits(dy, dtype)
+        want = oracle_bits(oracle.copy(n, x, ix, y, iy), dtype)
+        assert np.array_equal(got, want), (dtype, n, ix, iy, first_mismatch(got, want))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_axpy_strided(dtype):
+    T = tile(dtype)
+    for k, (n, ix, iy) in enumerate([(0, 2, 2), (1, 1, 1), (3000, 1, 1), (3000, 2, 3), (T + 5, -1, 2),
+                                     (4001, 3, -2), (513, 0, 1), (100003, -2, -1)]):
+        x = host_vec(n, ix, dtype, 2300 + k)
+        y = host_vec(n, iy, dtype, 2400 + k)
+        print("axpy_strided", dtype, n, ix, iy, flush=True)
+        dy = to_dev(y, dtype)
+        S.salt_axpy_strided(0.7, to_dev(x, dtype), dy, n, ix, iy)
+        got = to_host_bits(dy, dtype)
+        want = oracle_bits(oracle.axpy_strided(n, 0.7, x, ix, y, iy, dtype), dtype)
+        assert np.array_equal(got, want), (dtype, n, ix, iy, first_mismatch(got, want))
+
+
+# ---------------------------------------------------------------------------
+# reductions
+# ---------------------------------------------------------------------------
+
+def reduce_cases(dtype):
+    T = tile(dtype)
+    return [(0, 2, 3), (1, 3, 1), (5, -1, 2), (T - 1, 2, -3), (T + 1, 1, 2), (3 * T + 17, -2, -1),
+            (200003, 3, 0), (200003, 1, 1)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_dot_strided(dtype):
+    for k, (n, ix, iy) in enumerate(reduce_cases(dtype)):
+        x = host_vec(n, ix, dtype, 2500 + k)
+        y = host_vec(n, iy, dtype, 2600 + k)
+        print("dot_strided", dtype, n, ix, iy, flush=True)
+        got = scalar(S.salt_dot_strided(to_dev(x, dtype), to_dev(y, dtype), n, ix, iy))
+        gx, gy = oracle.gather(n, x, ix), oracle.gather(n, y, iy)
+        # the bits of the contiguous reduction of the gathered vectors
+        same = scalar(S.salt_dot(to_dev(gx, dtype), to_dev(gy, dtype), n=n)) if n > 0 else 0.0
+        assert got == same or (got == 0.0 and same == 0.0), (dtype, n, ix, iy, got, same)
+        ref, abs_sum = oracle.dot2(oracle.widen(gx, dtype), oracle.widen(gy, dtype))
+        assert abs(got - ref) <= oracle.TOL[dtype] * abs_sum, (dtype, n, got, ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_nrm2_strided_and_asum(dtype):
+    for k, (n, inc, _) in enumerate(reduce_cases(dtype)):
+        if inc <= 0:
+            inc = -inc + 1
+        x = host_vec(n, inc, dtype, 2700 + k)
+        d = to_dev(x, dtype)
+        gx = oracle.gather(n, x, inc)
+        w = oracle.widen(gx, dtype)
+        print("nrm2/asum strided", dtype, n, inc, flush=True)
+        nrm = scalar(S.salt_nrm2_strided(d, n, inc))
+        asm = scalar(S.salt_asum(d, n, inc))
+        if n == 0:
+            assert nrm == 0.0 and asm == 0.0
+            continue
+        dg = to_dev(gx, dtype)
+        assert nrm == scalar(S.salt_nrm2(dg, n=n)), (dtype, n, inc)
+        assert asm == scalar(S.salt_asum(dg, n, 1)), (dtype, n, inc)
+        ref = oracle.nrm2(w)
+        assert abs(nrm - ref) <= oracle.TOL[dtype] * ref, (dtype, n, nrm, ref)
+        aref, ascale = oracle.asum(w)
+        assert abs(asm - aref) <= oracle.TOL[dtype] * ascale, (dtype, n, asm, aref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_asum_contiguous_closed_form_and_alignment(dtype):
+    """sum |x_i| for x_i = +-(i mod 7) is an exact integer; unaligned views
+    give the same bits as aligned ones."""
+    T = tile(dtype)
+    for n in (1, 63, T, T + 9, 5 * T + 3):
+        i = np.arange(n)
+        v = ((i % 7) * np.where(i % 3 == 0, -1.0, 1.0)).astype(np.float32)
+        x = oracle.narrow(v, dtype) if dtype in ("bf16", "f16") else v.astype(oracle._NP[dtype])
+        want = float(np.sum(i % 7))
+        print("asum closed form", dtype, n, flush=True)
+        a = scalar(S.salt_asum(to_dev(x, dtype)))
+        b = scalar(S.salt_asum(to_dev(x, dtype, offset=1)))
+        assert a == want and b == want, (dtype, n, a, b, want)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_one_vector_routines_ignore_nonpositive_increments(dtype):
+    x = host_vec(10, 1, dtype, 2800)
+    d = to_dev(x, dtype)
+    for inc in (0, -1):
+        assert scalar(S.salt_nrm2_strided(d, 10, inc)) == 0.0
+        assert scalar(S.salt_asum(d, 10, inc)) == 0.0
+        r = S.salt_iamax(d, 10, inc)
+        sync()
+        assert int(r.item()) == -1
+
+
+# ---------------------------------------------------------------------------
+# iamax
+# ---------------------------------------------------------------------------
+
+def gpu_iamax(x, dtype, n, inc, offset=0):
+    r = S.salt_iamax(to_dev(x, dtype, offset=offset), n, inc)
+    sync()
+    return int(r.item())
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_iamax_random(dtype):
+    T = tile(dtype)
+    for k, (n, inc) in enumerate([(0, 1), (1, 1), (2, 1), (100, 1), (T - 1, 1), (T + 1, 1), (5 * T + 7, 1),
+                                  (5 * T + 7, 2), (1000003, 1), (100003, 7)]):
+        x = host_vec(n, inc, dtype, 2900 + k)
+        print("iamax", dtype, n, inc, flush=True)
+        want = oracle.iamax(n, x, inc, dtype)
+        assert gpu_iamax(x, dtype, n, inc) == want, (dtype, n, inc)
+        if inc == 1 and n > 0:
+            assert gpu_iamax(x, dtype, n, inc, offset=1) == want, (dtype, n, "unaligned")
+
+
+def stored(vals, dtype):
+    v = np.asarray(vals, dtype=np.float64)
+    if dtype in ("bf16", "f16"):
+        return oracle.narrow(v.astype(np.float32), dtype)
+    return v.astype(oracle._NP[dtype])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_iamax_ties_nans_and_infinities(dtype):
+    T = tile(dtype)
+    n = 3 * T + 11
+    rng = np.random.default_rng(31)
+    base = rng.uniform(-1, 1, n)
+    cases = []
+    # equal magnitudes in several tiles, with both signs: the first wins
+    v = base.copy()
+    for j in (T + 5, 2 * T + 1, 7, n - 1):
+        v[j] = -2.0 if j % 2 else 2.0
+    cases.append(("ties", v))
+    # NaNs are never chosen unless at index 0
+    v = base.copy()
+    v[[3, T, n - 2]] = np.nan
+    cases.append(("nan inside", v))
+    v = base.copy()
+    v[0] = np.nan
+    v[5] = 3.0
+    cases.append(("nan first", v))
+    cases.append(("all nan", np.full(n, np.nan)))
+    v = base.copy()
+    v[[T + 3, 2 * T]] = [-np.inf, np.inf]
+    cases.append(("infinities", v))
+    v = base.copy()
+    v[n - 1] = 5.0
+    cases.append(("max in ragged tail", v))
+    cases.append(("zeros", np.zeros(n) * np.where(np.arange(n) % 2, -1.0, 1.0)))
+    for name, vals in cases:
+        x = stored(vals, dtype)
+        print("iamax", dtype, name, flush=True)
+        for inc in (1, 2):
+            m = n if inc == 1 else (n + 1) // 2
+            want = oracle.iamax(m, x, inc, dtype)
+            assert gpu_iamax(x, dtype, m, inc) == want, (dtype, name, inc, want)
+
+
+def test_strided_dot_full_size():
+    """An FP32 strided dot over 2^24 elements (increment 3 and -2), against
+    the oracle within tolerance and against the contiguous call's bits."""
+    n = 1 << 24
+    x = host_vec(n, 3, "f32", 3100)
+    y = host_vec(n, -2, "f32", 3101)
+    print("strided dot full size", flush=True)
+    got = scalar(S.salt_dot_strided(to_dev(x, "f32"), to_dev(y, "f32"), n, 3, -2))
+    gx, gy = oracle.gather(n, x, 3), oracle.gather(n, y, -2)
+    assert got == scalar(S.salt_dot(to_dev(gx, "f32"), to_dev(gy, "f32")))
+    ref, abs_sum = oracle.dot2(gx.astype(np.float64), gy.astype(np.float64))
+    assert abs(got - ref) <= oracle.TOL["f32"] * abs_sum
