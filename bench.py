@@ -28,7 +28,7 @@ step):
                saturation rate, p50 / p99 latency and throughput.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
-                    [--sections main,sweep,fusion,precision,batched,served]
+                    [--sections main,sweep,fusion,precision,blas1,batched,served]
 """
 from __future__ import annotations
 
@@ -442,6 +442,50 @@ def section_precision(args):
 
 
 # ---------------------------------------------------------------------------
+# BLAS level-1 interface: asum, iamax and increments
+# ---------------------------------------------------------------------------
+
+def section_blas1(args):
+    """asum and iamax (contiguous, HBM read-bound) and the strided routines at
+    increments 2 and 4. Bytes are the algorithmic ones (elements the call
+    reads and writes); a strided call moves whole 64- or 128-byte lines, so
+    its useful bandwidth falls as the increment grows."""
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    n = 1 << args.log2n
+    log("bench: BLAS level-1, n = 2^%d" % args.log2n)
+    out = {"n": n, "dtype": "f64", "bytes": "algorithmic: 8 B per element read or written"}
+    x, y = workloads.uniform_device(n, "f64", workloads.sweep_seed(n) + 2, 2)
+    ws = salt.workspace(n, salt.F64)
+    r = torch.empty(1, dtype=torch.float64, device="cuda")
+    ri = torch.empty(1, dtype=torch.int64, device="cuda")
+    rows = {
+        "asum": (lambda: salt.salt_asum(x, n, 1, result=r, ws=ws), 8 * n),
+        "iamax": (lambda: salt.salt_iamax(x, n, 1, result=ri, ws=ws), 8 * n),
+        "nrm2": (lambda: salt.salt_nrm2(x, result=r, ws=ws), 8 * n),
+        "scal": (lambda: salt.salt_scal(1.0, y, n, 1), 16 * n),
+    }
+    for inc in (2, 4):
+        m = n // inc
+        rows["dot_inc%d" % inc] = (lambda m=m, inc=inc: salt.salt_dot_strided(x, y, m, inc, inc, result=r, ws=ws),
+                                   16 * m)
+        rows["asum_inc%d" % inc] = (lambda m=m, inc=inc: salt.salt_asum(x, m, inc, result=r, ws=ws), 8 * m)
+        rows["iamax_inc%d" % inc] = (lambda m=m, inc=inc: salt.salt_iamax(x, m, inc, result=ri, ws=ws), 8 * m)
+        rows["axpy_inc%d" % inc] = (lambda m=m, inc=inc: salt.salt_axpy_strided(1.0, x, y, m, inc, inc), 24 * m)
+        rows["copy_inc%d" % inc] = (lambda m=m, inc=inc: salt.salt_copy(x, y, m, inc, inc), 16 * m)
+    for name, (fn, nbytes) in rows.items():
+        t = event_ms(fn, 10)
+        out[name] = {"ms": round(t, 4), "GBps": round(nbytes / (t * 1e-3) / 1e9, 1),
+                     "frac_of_8TBps": round(nbytes / (t * 1e-3) / 8e12, 3)}
+    del x, y, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # batched layer
 # ---------------------------------------------------------------------------
 
@@ -553,7 +597,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--sections", default="main,sweep,fusion,precision,batched,served")
+    ap.add_argument("--sections", default="main,sweep,fusion,precision,blas1,batched,served")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-log2n", type=int, default=26)
@@ -587,6 +631,8 @@ def main() -> int:
         out["fusion"] = section_fusion(args)
     if "precision" in sections:
         out["precision"] = section_precision(args)
+    if "blas1" in sections:
+        out["blas1"] = section_blas1(args)
     if "batched" in sections:
         out["batched"] = section_batched(args)
     if "served" in sections:

@@ -16,7 +16,8 @@
 //    kernel's canonical order (tile, lane, chunk, slot), element by element;
 //    pass 2 is the contiguous one. A strided reduction therefore has the same
 //    bits as the contiguous reduction of the gathered vectors.
-//  * k_iamax_pass1 / k_iamax_pass2: first index of the largest magnitude.
+//  * k_iamax_pass1 / k_iamax_pass2a / k_iamax_pass2: first index of the
+//    largest magnitude.
 //    The order "larger magnitude, then smaller index" is total, so the tree
 //    of comparisons gives the scan's answer whatever its shape. A NaN never
 //    wins (its key is below every magnitude) except as element 0, which the
@@ -220,37 +221,57 @@ __device__ __forceinline__ Amax<DT> block_best(Amax<DT> b, typename Amax<DT>::K 
 }
 
 // Pass 1: per tile of T elements (the reductions' tile), the index of its
-// best element. Unit stride with aligned data reads whole 16-byte chunks.
+// best element. Each lane visits its elements in increasing index order, so a
+// plain "greater magnitude" test keeps the first of equal magnitudes, and a
+// NaN fails the test; the lane starts from its first element with key -1, so
+// a lane of NaNs still names one of its own elements (which pass 2 rates
+// below every magnitude). Unit stride with aligned data loads whole 16-byte
+// chunks.
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_iamax_pass1(IamaxLaunch a) {
     using K = typename Amax<DT>::K;
     constexpr int V = Tr<DT>::V;
     constexpr int64_t T = tile_elems<DT>();
+    constexpr int B = 8;  // chunks per load burst
     const int64_t n_tiles = (a.n + T - 1) / T;
     __shared__ K lkey[kBlock / 64];
     __shared__ int64_t lidx[kBlock / 64];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        Amax<DT> best{(K)-2, INT64_MAX};  // below every key: any element replaces it
         const int64_t c0 = t * ((int64_t)kBlock * kChunksPerLane) + threadIdx.x;
+        const int64_t j0 = c0 * V;  // this lane's first element
+        Amax<DT> best{j0 < a.n ? (K)-1 : (K)-2, j0 < a.n ? j0 : INT64_MAX};
         const bool whole = a.vec && (t + 1) * T <= a.n;
         if (whole) {
 #pragma unroll
-            for (int it0 = 0; it0 < kChunksPerLane; it0 += 4) {
-                u32x4 raw[4];
+            for (int it0 = 0; it0 < kChunksPerLane; it0 += B) {
+                u32x4 raw[B];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) raw[u] = ld16<true>((const u32x4 *)a.x + c0 + (int64_t)(it0 + u) * kBlock);
+                for (int u = 0; u < B; ++u) raw[u] = ld16<true>((const u32x4 *)a.x + c0 + (int64_t)(it0 + u) * kBlock);
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < B; ++u)
 #pragma unroll
-                    for (int p = 0; p < V; ++p)
-                        best.take(Amax<DT>::key_of(Tr<DT>::get(raw[u], p)), (c0 + (int64_t)(it0 + u) * kBlock) * V + p);
+                    for (int p = 0; p < V; ++p) {
+                        const K v = Tr<DT>::get(raw[u], p);
+                        const K m = v < (K)0 ? -v : v;
+                        if (m > best.key) {
+                            best.key = m;
+                            best.idx = (c0 + (int64_t)(it0 + u) * kBlock) * V + p;
+                        }
+                    }
             }
         } else {
             for (int it = 0; it < kChunksPerLane; ++it)
 #pragma unroll
                 for (int p = 0; p < V; ++p) {
                     const int64_t j = (c0 + (int64_t)it * kBlock) * V + p;
-                    if (j < a.n) best.take(Amax<DT>::key_of(Tr<DT>::ld1(a.x, j * a.inc)), j);
+                    if (j < a.n) {
+                        const K v = Tr<DT>::ld1(a.x, j * a.inc);
+                        const K m = v < (K)0 ? -v : v;
+                        if (m > best.key) {
+                            best.key = m;
+                            best.idx = j;
+                        }
+                    }
                 }
         }
         best = block_best<DT, kBlock / 64>(best, lkey, lidx);
@@ -258,12 +279,30 @@ __global__ __launch_bounds__(kBlock) void k_iamax_pass1(IamaxLaunch a) {
     }
 }
 
-// Pass 2: one workgroup over the tiles' candidates; writes the index, 0 when
-// element 0 is NaN, -1 for an empty vector.
+// Pass 2a (many tiles): workgroup b rates candidates b*1024 ... b*1024+1023,
+// one gather per lane, and writes its winner over the first of them (a slot
+// no other workgroup reads). A single workgroup doing every gather would be
+// limited by one CU's rate of cache-line requests.
 template <int DT>
-__global__ __launch_bounds__(kFinalBlock) void k_iamax_pass2(IamaxLaunch a) {
+__global__ __launch_bounds__(kFinalBlock) void k_iamax_pass2a(IamaxLaunch a, int64_t count) {
     using K = typename Amax<DT>::K;
-    constexpr int64_t T = tile_elems<DT>();
+    __shared__ K lkey[kFinalBlock / 64];
+    __shared__ int64_t lidx[kFinalBlock / 64];
+    const int64_t t = (int64_t)blockIdx.x * kFinalBlock + threadIdx.x;
+    Amax<DT> best{(K)-2, INT64_MAX};
+    if (t < count) {
+        const int64_t j = a.ws[t];
+        best = Amax<DT>{Amax<DT>::key_of(Tr<DT>::ld1(a.x, j * a.inc)), j};
+    }
+    best = block_best<DT, kFinalBlock / 64>(best, lkey, lidx);
+    if (threadIdx.x == 0) a.ws[(int64_t)blockIdx.x * kFinalBlock] = best.idx;
+}
+
+// Pass 2: one workgroup over the candidates ws[0], ws[stride], ... (count of
+// them); writes the index, 0 when element 0 is NaN, -1 for an empty vector.
+template <int DT>
+__global__ __launch_bounds__(kFinalBlock) void k_iamax_pass2(IamaxLaunch a, int64_t count, int64_t stride) {
+    using K = typename Amax<DT>::K;
     __shared__ K lkey[kFinalBlock / 64];
     __shared__ int64_t lidx[kFinalBlock / 64];
     if (a.n < 1) {
@@ -275,11 +314,23 @@ __global__ __launch_bounds__(kFinalBlock) void k_iamax_pass2(IamaxLaunch a) {
         if (threadIdx.x == 0) *a.result = 0;
         return;
     }
-    const int64_t n_tiles = (a.n + T - 1) / T;
     Amax<DT> best{(K)-2, INT64_MAX};
-    for (int64_t t = threadIdx.x; t < n_tiles; t += kFinalBlock) {
-        const int64_t j = a.ws[t];
-        best.take(Amax<DT>::key_of(Tr<DT>::ld1(a.x, j * a.inc)), j);
+    // Candidates eight at a time: their indices, then their values, each as
+    // one round of independent loads.
+    constexpr int Q = 8;
+    for (int64_t c0 = threadIdx.x; c0 < count; c0 += Q * kFinalBlock) {
+        int64_t j[Q];
+        K v[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t c = c0 + (int64_t)q * kFinalBlock;
+            j[q] = c < count ? a.ws[c * stride] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = j[q] >= 0 ? Tr<DT>::ld1(a.x, j[q] * a.inc) : (K)0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (j[q] >= 0) best.take(Amax<DT>::key_of(v[q]), j[q]);
     }
     best = block_best<DT, kFinalBlock / 64>(best, lkey, lidx);
     if (threadIdx.x == 0) *a.result = best.idx;
@@ -289,13 +340,22 @@ template <int DT>
 static hipError_t launch_iamax_dt(const IamaxLaunch &L) {
     constexpr int64_t T = tile_elems<DT>();
     const int64_t n_tiles = L.n > 0 ? (L.n + T - 1) / T : 0;
+    int64_t count = n_tiles, stride = 1;
     if (n_tiles > 0) {
         const int64_t grid = n_tiles < 0x7fffffff ? n_tiles : 0x7fffffff;
         hipLaunchKernelGGL((k_iamax_pass1<DT>), dim3((unsigned)grid), dim3(kBlock), 0, (hipStream_t)L.stream, L);
-        const hipError_t e = hipGetLastError();
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (n_tiles > kFinalBlock) {
+            count = (n_tiles + kFinalBlock - 1) / kFinalBlock;
+            stride = kFinalBlock;
+            hipLaunchKernelGGL((k_iamax_pass2a<DT>), dim3((unsigned)count), dim3(kFinalBlock), 0,
+                               (hipStream_t)L.stream, L, n_tiles);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
-    hipLaunchKernelGGL((k_iamax_pass2<DT>), dim3(1), dim3(kFinalBlock), 0, (hipStream_t)L.stream, L);
+    hipLaunchKernelGGL((k_iamax_pass2<DT>), dim3(1), dim3(kFinalBlock), 0, (hipStream_t)L.stream, L, count, stride);
     return hipGetLastError();
 }
 

@@ -247,3 +247,20 @@ def test_strided_dot_full_size():
     assert got == scalar(S.salt_dot(to_dev(gx, "f32"), to_dev(gy, "f32")))
     ref, abs_sum = oracle.dot2(gx.astype(np.float64), gy.astype(np.float64))
     assert abs(got - ref) <= oracle.TOL["f32"] * abs_sum
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_iamax_more_tiles_than_one_combine_pass(dtype):
+    """More than 1024 tiles: the candidates go through the many-workgroup
+    pass before the last one. A tie planted across far-apart tiles."""
+    T = tile(dtype)
+    n = 1100 * T + 5
+    for inc, seed in ((1, 3200), (2, 3201)):
+        m = n
+        x = host_vec(m, inc, dtype, seed)
+        x[(3 * T + 11) * inc] = -1.5
+        x[(1050 * T + 2) * inc] = 1.5
+        print("iamax many tiles", dtype, m, inc, flush=True)
+        want = oracle.iamax(m, x, inc, dtype)
+        assert want == 3 * T + 11
+        assert gpu_iamax(x, dtype, m, inc) == want
