@@ -33,7 +33,7 @@ def _torch_dtype(d):
 def candidates(kind: str, n: int, dtype: int, cus: int):
     unrolls = {"eval": (1, 2, 4, 8), "interp": (1, 2, 4), "batch": (2, 4, 8), "dotx": (2, 4, 8),
                "nrm2x": (2, 4, 8)}.get(kind, (2, 4, 8, 16))
-    grids = [0] + [cus * k for k in ((1, 2, 4, 8) if kind == "batch" else (1, 2, 4, 8, 16))]
+    grids = [0] + [cus * k for k in (1, 2, 4, 8, 16)]
     out = []
     for u in unrolls:
         for nt in (0, 1):
