@@ -329,8 +329,9 @@ void salt_batch_plan_destroy(salt_batch_plan plan);
  * so requests that arrive while others run are admitted and overlap with
  * them on the device (continuous batching). Completion times are the GPU
  * events of the batch, mapped to the host clock. Everything runs on the
- * calling thread; the call returns when every request has completed or been
- * rejected. */
+ * calling thread; the call first waits for the device to be idle (work the
+ * caller queued on any stream, such as filling the operands, completes
+ * first) and returns when every request has completed or been rejected. */
 typedef struct {
     void *arena;             /* device memory for outputs (caller-owned)      */
     size_t arena_bytes;

@@ -180,6 +180,10 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
         for (auto &x : sl.ev)
             if ((e = hipEventCreate(&x)) != hipSuccess) return dev_fail(e);
     }
+    // The loop's streams do not wait for the caller's: operands (and the
+    // arenas' previous users) may still be busy on other streams, so the
+    // device must be idle before the first copy or launch.
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return dev_fail(e);
     if ((e = hipEventCreate(&ev0)) != hipSuccess) return dev_fail(e);
     if ((e = hipEventRecord(ev0, streams[0])) != hipSuccess) return dev_fail(e);
     if ((e = hipEventSynchronize(ev0)) != hipSuccess) return dev_fail(e);
