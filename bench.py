@@ -427,8 +427,8 @@ def section_precision(args):
             "dot_ms": round(t_dot, 4), "dot_GBps": round(2 * es * n / (t_dot * 1e-3) / 1e9, 1),
             "nrm2_ms": round(t_nrm, 4), "nrm2_GBps": round(es * n / (t_nrm * 1e-3) / 1e9, 1),
             "accumulation": "binary64 fma" if name == "f64" else
-                            ("compensated binary32 (TwoProduct+TwoSum), binary64 combine" if name == "f32" else
-                             "exact binary32 products summed in binary64"),
+                            ("compensated binary32 (TwoProduct+TwoSum)" if name == "f32" else
+                             "compensated binary32 (exact products, TwoSum)") + ", binary64 combine",
             # (i) end to end, including storage rounding, vs the binary64 data
             "dot_err_vs_f64_data": abs(got_dot - exact_dot) / abs_dot,
             "nrm2_err_vs_f64_data": abs(got_nrm - exact_nrm) / exact_nrm,

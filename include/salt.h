@@ -107,9 +107,8 @@ size_t salt_reduce_workspace_bytes(int64_t n, salt_dtype dtype);
  * Sec. 4.2, the reduction step). The summation order depends only on n and
  * dtype (fixed tiles, fixed in-tile order, fixed tree over tiles), so the
  * result is bit-reproducible across calls, launch shapes and batching.
- * Accumulation per lane: binary64 fma for F64; compensated binary32
- * (error-free products and sums) for F32; for BF16/F16 the exact binary32
- * products summed in binary64. Binary64 across lanes and tiles.
+ * Accumulation: binary64 for F64; for F32/BF16/F16 compensated binary32
+ * (error-free products and sums) per lane, binary64 across lanes and tiles.
  *  result     device pointer to one double (F64) or one float (others)
  *  workspace  device buffer, 8-byte aligned, >= salt_reduce_workspace_bytes */
 salt_status salt_dot(int64_t n, const void *x, const void *y, void *result,

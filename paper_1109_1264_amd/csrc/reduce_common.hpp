@@ -13,9 +13,8 @@
 // partials l, l+1024, ... in order; the same butterfly; a pairwise tree over
 // the 16 wave sums.
 // Accumulators: binary64 fused multiply-add for binary64 storage;
-// compensated binary32 for binary32 storage (TwoProduct with one fma, TwoSum
-// for every addition); for 16-bit storage the exact binary32 products summed
-// in binary64.
+// compensated binary32 otherwise (TwoProduct with one fma for binary32
+// inputs, exact products for 16-bit inputs, TwoSum for every addition).
 #pragma once
 
 #include "device.hpp"
@@ -58,16 +57,14 @@ struct Acc<SALT_F32> {
     __device__ __forceinline__ double value() const { return (double)s + (double)c; }
 };
 
-// 16-bit storage: the product of two bfloat16 (8-bit significands) or two
-// binary16 values (11-bit) is exact in binary32, and so is its widening to
-// binary64; the running sum is kept in binary64. Three VALU operations per
-// element (multiply, widen, add) where a compensated binary32 sum takes
-// seven: at two bytes per element the compensated form is close to the
-// VALU's rate, and the binary64 sum is also the more accurate.
 struct AccExactProduct {
-    double s = 0.0;
-    __device__ __forceinline__ void add(float x, float y) { s = s + (double)(x * y); }
-    __device__ __forceinline__ double value() const { return s; }
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float x, float y) {
+        float e;
+        two_sum(s, x * y, s, e);  // the product of two 16-bit values is exact
+        c = c + e;
+    }
+    __device__ __forceinline__ double value() const { return (double)s + (double)c; }
 };
 template <> struct Acc<SALT_BF16> : AccExactProduct {};
 template <> struct Acc<SALT_F16> : AccExactProduct {};
