@@ -195,6 +195,12 @@ def section_main(args, out):
 
     copy_ms = event_ms(lambda: launch("copy"), 20)
     copy_gbps = 16.0 * n / (copy_ms * 1e-3) / 1e9
+    # references outside this library, on the same buffers: torch's own copy
+    # (the framework's bandwidth ceiling for one read + one write stream) and
+    # the tree as five unfused torch operations (each intermediate goes
+    # through HBM)
+    torch_copy_ms = event_ms(lambda: d.copy_(a), 20)
+    torch_tree_ms = event_ms(lambda: torch.sub(torch.add(torch.mul(a, b), torch.mul(c, e)), f, out=d), 10)
     kernels = {k: {"avg_ms": round(per[k], 4), "GBps": round(bytes_per_elem[k] * n / (per[k] * 1e-3) / 1e9, 1),
                    "bytes_per_elem": bytes_per_elem[k],
                    "launch_config": salt.salt_tuning_lookup(0 if k in ("tree5", "axpy") else (1 if k == "dot" else 2),
@@ -214,6 +220,10 @@ def section_main(args, out):
         "kernels": kernels,
         "copy_ceiling": {"avg_ms": round(copy_ms, 4), "GBps": round(copy_gbps, 1),
                          "pct_of_hbm_peak": round(100 * copy_gbps / HBM_PEAK_GBPS, 2)},
+        "torch_reference": {"copy_ms": round(torch_copy_ms, 4),
+                            "copy_GBps": round(16.0 * n / (torch_copy_ms * 1e-3) / 1e9, 1),
+                            "tree5_unfused_ms": round(torch_tree_ms, 4),
+                            "tree5_fused_speedup": round(torch_tree_ms / per["tree5"], 3)},
     })
     if not args.no_parity:
         out["parity"] = main_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5)
