@@ -191,6 +191,29 @@ salt_status salt_asum(int64_t n, const void *x, int64_t incx, void *result,
 salt_status salt_iamax(int64_t n, const void *x, int64_t incx, int64_t *result,
                        void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream);
 
+/* ---- sharded reductions ------------------------------------------------------
+ * The two passes of salt_dot / salt_nrm2 / salt_asum as separate calls, for a
+ * vector split into shards (on several devices, or processed piecewise). A
+ * shard boundary must fall on a tile boundary: every shard except the last
+ * holds a multiple of salt_reduce_tile_elems(dtype) elements. Then the
+ * shards' partials, placed side by side in shard order, are exactly the
+ * partials of the whole vector, and combining them gives the bits of the
+ * one-call result, for any number of shards (on several GPUs the partials,
+ * 8 bytes per tile, are gathered to one device and combined there).
+ *  mode  0: dot (x, y), 1: nrm2 (x), 2: asum (x); y is ignored unless dot. */
+
+/* Pass 1 over the n elements of one shard: ceil(n / tile) binary64 partials,
+ * in tile order, to `partials` (device, 8-byte aligned, not overlapping x or
+ * y). Unit increments only. */
+salt_status salt_reduce_partials(int32_t mode, int64_t n, const void *x, const void *y, double *partials,
+                                 salt_dtype dtype, void *hip_stream);
+
+/* Pass 2: the fixed combine of `count` partials (device) into the device
+ * scalar `result` (double for F64, float otherwise; the square root for
+ * nrm2). count = 0 gives 0. */
+salt_status salt_reduce_combine(int32_t mode, const double *partials, int64_t count, void *result,
+                                salt_dtype dtype, void *hip_stream);
+
 /* ---- launch control (autotuning and introspection) ------------------------
  * The paper picks the number of instruction packages per loop by trial
  * (Sec. 4.3); here the equivalent knobs are chosen per tree, element type

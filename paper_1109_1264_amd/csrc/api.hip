@@ -289,6 +289,8 @@ salt_status reduce_impl(int64_t n, const void *x, const void *y, void *result, v
     L.nontemporal = c.nontemporal;
     L.blocks = c.blocks;
     L.mode = mode;
+    L.passes = 3;
+    L.n_partials = 0;
     L.stream = stream;
     return device_status(launch_reduce(L, dtype));
 }
@@ -522,6 +524,59 @@ salt_status salt_dot(int64_t n, const void *x, const void *y, void *result, void
 salt_status salt_dot_ex(int64_t n, const void *x, const void *y, void *result, void *workspace,
                         size_t ws_bytes, salt_dtype dtype, void *hip_stream, const salt_launch_config *cfg) {
     return reduce_impl(n, x, y, result, workspace, ws_bytes, dtype, hip_stream, cfg, kModeDot);
+}
+
+salt_status salt_reduce_partials(int32_t mode, int64_t n, const void *x, const void *y, double *partials,
+                                 salt_dtype dtype, void *hip_stream) {
+    if (mode < kModeDot || mode > kModeAsum) return fail(SALT_ERR_ARG, "mode " + std::to_string(mode) + " outside 0..2");
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    if ((uint64_t)n > (uint64_t)INT64_MAX / 16) return fail(SALT_ERR_ARG, "length too large");
+    const bool two = mode == kModeDot;
+    if (n == 0) return SALT_OK;  // no tiles, no partials
+    if (!x || (two && !y)) return fail(SALT_ERR_ARG, "input pointer is NULL");
+    if (!partials) return fail(SALT_ERR_ARG, "partials pointer is NULL");
+    if (((uintptr_t)partials & 7u) != 0) return fail(SALT_ERR_ARG, "partials not 8-byte aligned");
+    const size_t need = salt_reduce_workspace_bytes(n, dtype), bytes = (size_t)n * esize(dtype);
+    if (any_overlap(partials, need, x, bytes) || (two && any_overlap(partials, need, y, bytes)))
+        return fail(SALT_ERR_ARG, "partials overlap an input");
+    salt_launch_config c;
+    salt_status s = resolve(nullptr, lookup(two ? kDot : kNrm2, -1, dtype, n, two ? 2 : 1), two ? kDot : kNrm2, &c);
+    if (s != SALT_OK) return s;
+    ReduceLaunch L;
+    L.x = x;
+    L.y = two ? y : x;
+    L.result = nullptr;
+    L.ws = partials;
+    L.n = n;
+    L.vec = aligned16(x) && (!two || aligned16(y)) ? 1 : 0;
+    L.unroll = c.unroll;
+    L.nontemporal = c.nontemporal;
+    L.blocks = c.blocks;
+    L.mode = mode;
+    L.passes = 1;
+    L.n_partials = 0;
+    L.stream = hip_stream;
+    return device_status(launch_reduce(L, dtype));
+}
+
+salt_status salt_reduce_combine(int32_t mode, const double *partials, int64_t count, void *result, salt_dtype dtype,
+                                void *hip_stream) {
+    if (mode < kModeDot || mode > kModeAsum) return fail(SALT_ERR_ARG, "mode " + std::to_string(mode) + " outside 0..2");
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    if (count < 0) return fail(SALT_ERR_ARG, "negative partial count");
+    if (!result) return fail(SALT_ERR_ARG, "result pointer is NULL");
+    if (count > 0 && !partials) return fail(SALT_ERR_ARG, "partials pointer is NULL");
+    if (((uintptr_t)partials & 7u) != 0) return fail(SALT_ERR_ARG, "partials not 8-byte aligned");
+    ReduceLaunch L;
+    std::memset(&L, 0, sizeof L);
+    L.result = result;
+    L.ws = const_cast<double *>(partials);
+    L.mode = mode;
+    L.passes = 2;
+    L.n_partials = count;
+    L.stream = hip_stream;
+    return device_status(launch_reduce(L, dtype));
 }
 
 salt_status salt_scal(int64_t n, double alpha, void *x, int64_t incx, salt_dtype dtype, void *hip_stream) {

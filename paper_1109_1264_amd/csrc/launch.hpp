@@ -48,6 +48,8 @@ struct ReduceLaunch {
     int32_t nontemporal;
     int64_t blocks;     // 0 = one workgroup per tile, else grid size
     int32_t mode;       // ReduceMode
+    int32_t passes;     // bit 0: pass 1 (partials into ws), bit 1: pass 2 (ws -> result)
+    int64_t n_partials; // pass 2 alone: the partials in ws
     void *stream;
 };
 int64_t reduce_tile_elems(int dtype);

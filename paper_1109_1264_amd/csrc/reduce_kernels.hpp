@@ -191,8 +191,8 @@ static void pass1_dispatch(const ReduceLaunch &L, int64_t grid) {
 template <int DT>
 static hipError_t launch_reduce_dt(const ReduceLaunch &L) {
     const int64_t T = tile_elems<DT>();
-    const int64_t n_tiles = (L.n + T - 1) / T;
-    if (n_tiles > 0) {
+    const int64_t n_tiles = (L.passes & 1) ? (L.n + T - 1) / T : L.n_partials;
+    if ((L.passes & 1) && n_tiles > 0) {
         int64_t grid = L.blocks > 0 && L.blocks < n_tiles ? L.blocks : n_tiles;
         if (grid > 0x7fffffff) grid = 0x7fffffff;
         if (L.mode == kModeNrm2) pass1_dispatch<DT, kModeNrm2>(L, grid);
@@ -201,6 +201,7 @@ static hipError_t launch_reduce_dt(const ReduceLaunch &L) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (!(L.passes & 2)) return hipSuccess;
     if (L.mode == kModeNrm2)
         hipLaunchKernelGGL((k_reduce_pass2<DT, true>), dim3(1), dim3(kFinalBlock), 0, (hipStream_t)L.stream,
                            (const double *)L.ws, n_tiles, L.result);

@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
         "salt_dot_ex": ([I64, P, P, P, P, SZ, I32, P, CFG], I32),
         "salt_nrm2": ([I64, P, P, P, SZ, I32, P], I32),
         "salt_nrm2_ex": ([I64, P, P, P, SZ, I32, P, CFG], I32),
+        "salt_reduce_partials": ([I32, I64, P, P, P, I32, P], I32),
+        "salt_reduce_combine": ([I32, P, I64, P, I32, P], I32),
         "salt_scal": ([I64, D, P, I64, I32, P], I32),
         "salt_copy": ([I64, P, I64, P, I64, I32, P], I32),
         "salt_axpy_strided": ([I64, D, P, I64, P, I64, I32, P], I32),
@@ -279,6 +281,40 @@ def salt_nrm2(x, n: int | None = None, result=None, ws=None, stream=None, config
     else:
         st = L.salt_nrm2_ex(n, _dev(x), _dev(result), _dev(ws), nb, d, _stream_ptr(stream), _cfg(config))
     check(st)
+    return result
+
+
+# ---------------------------------------------------------------------------
+# sharded reductions: pass 1 per shard (shards split at tile boundaries),
+# pass 2 over the partials placed side by side
+# ---------------------------------------------------------------------------
+
+MODE_DOT, MODE_NRM2, MODE_ASUM = 0, 1, 2
+
+
+def salt_reduce_partials(mode: int, x, y=None, n: int | None = None, partials=None, stream=None):
+    """Device float64 tensor of the ceil(n / tile) partials of one shard."""
+    import torch
+
+    d = dtype_code(x)
+    if n is None:
+        n = x.numel()
+    if mode == MODE_DOT and (y is None or dtype_code(y) != d):
+        raise TypeError("dot needs y of the same dtype")
+    count = (n + salt_reduce_tile_elems(d) - 1) // salt_reduce_tile_elems(d)
+    if partials is None:
+        partials = torch.empty(max(count, 1), dtype=torch.float64, device=x.device)
+    check(lib().salt_reduce_partials(mode, n, _dev(x), _dev(y) if y is not None else None, _dev(partials), d,
+                                     _stream_ptr(stream)))
+    return partials[:count]
+
+
+def salt_reduce_combine(mode: int, partials, dtype: int, count: int | None = None, result=None, stream=None):
+    """Device scalar from partials (the fixed pass-2 combine)."""
+    if count is None:
+        count = partials.numel()
+    result = _result_tensor(dtype, partials.device) if result is None else result
+    check(lib().salt_reduce_combine(mode, _dev(partials), count, _dev(result), dtype, _stream_ptr(stream)))
     return result
 
 

@@ -270,3 +270,21 @@ def test_blas1_strided_argument_errors(L):
     assert L.salt_iamax(n, X, inc, R + 4, W, need, F64, None) == S.ERR_ARG
     assert L.salt_iamax(n, X, inc, R, W, need - 8, F64, None) == S.ERR_WORKSPACE
     assert L.salt_iamax(n, None, inc, R, W, need, F64, None) == S.ERR_ARG
+
+
+def test_sharded_reduction_argument_errors(L):
+    X, Y, P, R = 0x1000000, 0x2000000, 0x3000000, 0x4000000
+    n = 100000
+    assert L.salt_reduce_partials(3, n, X, Y, P, S.F64, None) == S.ERR_ARG           # mode
+    assert L.salt_reduce_partials(0, -1, X, Y, P, S.F64, None) == S.ERR_ARG
+    assert L.salt_reduce_partials(0, n, X, None, P, S.F64, None) == S.ERR_ARG        # dot needs y
+    assert L.salt_reduce_partials(1, n, X, None, None, S.F64, None) == S.ERR_ARG     # no partials
+    assert L.salt_reduce_partials(1, n, X, None, P + 4, S.F64, None) == S.ERR_ARG    # misaligned
+    assert L.salt_reduce_partials(1, n, X, None, X + 64, S.F64, None) == S.ERR_ARG   # overlaps x
+    assert L.salt_reduce_partials(0, n, X, Y, P, 7, None) == S.ERR_ARG               # dtype
+    assert L.salt_reduce_partials(2, 0, None, None, None, S.F32, None) == S.OK       # empty shard: nothing to do
+    assert L.salt_reduce_combine(-1, P, 4, R, S.F64, None) == S.ERR_ARG
+    assert L.salt_reduce_combine(0, P, -1, R, S.F64, None) == S.ERR_ARG
+    assert L.salt_reduce_combine(0, P, 4, None, S.F64, None) == S.ERR_ARG
+    assert L.salt_reduce_combine(0, None, 4, R, S.F64, None) == S.ERR_ARG
+    assert L.salt_reduce_combine(0, P + 2, 4, R, S.F64, None) == S.ERR_ARG
