@@ -52,22 +52,6 @@ __device__ __forceinline__ void gst16(void *p, int64_t ci, u32x4 v) {
     else *g = v;
 }
 
-// Raw buffer resource over `bytes` bytes from p (stride 0; the last word is
-// the gfx9-family data-format field). The hardware checks every access
-// against the size: loads past it return zero and stores past it are dropped,
-// so a ragged tile needs no per-chunk branches.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
-}
-template <bool NT>
-__device__ __forceinline__ u32x4 bld16(__amdgpu_buffer_rsrc_t r, int32_t off) {
-    return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? 2 : 0);
-}
-template <bool NT>
-__device__ __forceinline__ void bst16(__amdgpu_buffer_rsrc_t r, int32_t off, u32x4 v) {
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, NT ? 2 : 0);
-}
-
 // Shape of one tile of one item.
 enum TileForm {
     kWhole = 0,    // inside the item, arrays aligned: plain 16-byte accesses

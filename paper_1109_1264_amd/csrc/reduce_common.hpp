@@ -119,6 +119,22 @@ __device__ __forceinline__ u32x4 load_chunk_guarded(const void *p, int64_t ci, i
     return Tr<DT>::template pack<V>(v);
 }
 
+// Raw buffer resource over `bytes` bytes from p (stride 0; the last word is
+// the gfx9-family data-format field). The hardware checks every access
+// against the size: loads past it return zero and stores past it are dropped,
+// so a ragged tile needs no per-chunk branches.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+template <bool NT>
+__device__ __forceinline__ u32x4 bld16(__amdgpu_buffer_rsrc_t r, int32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? 2 : 0);
+}
+template <bool NT>
+__device__ __forceinline__ void bst16(__amdgpu_buffer_rsrc_t r, int32_t off, u32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, NT ? 2 : 0);
+}
+
 // Final combine over `count` partials by one workgroup of kFinalBlock lanes:
 // lane l adds partials l, l + 1024, l + 2048, ... in that order (loaded 8 at
 // a time), then block_sum. The value is returned in every thread.

@@ -27,6 +27,12 @@ struct RedArgs {
     double *ws;
     int64_t n;
     int32_t vec;
+    // A single tile (n <= tile size): the combine of one partial is the
+    // partial itself (it is never -0, so adding the zeros of the other lanes
+    // keeps its bits), so pass 1 rounds and stores the result directly and
+    // pass 2 is not launched.
+    void *result;
+    int32_t final_store;
 };
 
 // The value a reduction adds for element (x, y): x*y (dot), x*x (nrm2), or
@@ -53,6 +59,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pass1(RedArgs a) {
         Acc<DT> acc[V];
         const int64_t c0 = t * ((int64_t)kBlock * kChunksPerLane) + threadIdx.x;
         const bool full = t < n_full;
+        // The last tile of aligned arrays: range-checked buffer loads over its
+        // whole chunks (zeros past them), and the chunk that straddles the
+        // end, if any, element by element by its lane. Same values as the
+        // element-wise path, without a branch per chunk.
+        const bool ragged = !full && a.vec;
+        const int64_t m = a.n - t * T;
+        const int32_t whole = ragged ? (int32_t)(m / V) : 0;
+        const int32_t straddle = ragged && (m % V) ? whole : -1;
+        __amdgpu_buffer_rsrc_t rx, ry;
+        if (ragged) {
+            rx = rsrc((const typename Tr<DT>::S *)a.x + t * T, whole * 16);
+            ry = rsrc((const typename Tr<DT>::S *)(NRM ? a.x : a.y) + t * T, whole * 16);
+        }
 #pragma unroll
         for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
             u32x4 xr[UR], yr[UR];
@@ -62,6 +81,20 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pass1(RedArgs a) {
                     xr[u] = ld16<NT>(x16 + c0 + (int64_t)(it0 + u) * kBlock);
                     if constexpr (!NRM) yr[u] = ld16<NT>(y16 + c0 + (int64_t)(it0 + u) * kBlock);
                 }
+            } else if (ragged) {
+#pragma unroll
+                for (int u = 0; u < UR; ++u) {
+                    const int32_t off = ((it0 + u) * kBlock + (int32_t)threadIdx.x) * 16;
+                    xr[u] = bld16<NT>(rx, off);
+                    if constexpr (!NRM) yr[u] = bld16<NT>(ry, off);
+                }
+#pragma unroll
+                for (int u = 0; u < UR; ++u)
+                    if (straddle >= 0 && it0 + u == straddle / kBlock && (int)threadIdx.x == straddle % kBlock) {
+                        const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
+                        xr[u] = load_chunk_guarded<DT, NT>(a.x, ci, a.n, false);
+                        if constexpr (!NRM) yr[u] = load_chunk_guarded<DT, NT>(a.y, ci, a.n, false);
+                    }
             } else {
 #pragma unroll
                 for (int u = 0; u < UR; ++u) {
@@ -79,7 +112,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pass1(RedArgs a) {
                 }
         }
         const double v = block_sum<kBlock / 64>(lane_value<DT>(acc), lds);
-        if (threadIdx.x == 0) a.ws[t] = v;
+        if (threadIdx.x == 0) {
+            if (a.final_store) store_result<DT, MODE == kModeNrm2>(a.result, v);
+            else a.ws[t] = v;
+        }
     }
 }
 
@@ -172,7 +208,9 @@ __global__ __launch_bounds__(kFinalBlock) void k_reduce_pass2(const double *ws, 
 
 template <int DT, int UR, bool NT, int MODE>
 static void launch_pass1(const ReduceLaunch &L, int64_t grid) {
-    RedArgs a{L.x, L.y, L.ws, L.n, L.vec};
+    const int64_t T = tile_elems<DT>();
+    const int final_store = (L.passes == 3 && L.n <= T) ? 1 : 0;
+    RedArgs a{L.x, L.y, L.ws, L.n, L.vec, L.result, final_store};
     hipLaunchKernelGGL((k_reduce_pass1<DT, UR, NT, MODE>), dim3((unsigned)grid), dim3(kBlock), 0,
                        (hipStream_t)L.stream, a);
 }
@@ -201,7 +239,7 @@ static hipError_t launch_reduce_dt(const ReduceLaunch &L) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (!(L.passes & 2)) return hipSuccess;
+    if (!(L.passes & 2) || ((L.passes & 1) && n_tiles == 1)) return hipSuccess;  // pass 1 stored it
     if (L.mode == kModeNrm2)
         hipLaunchKernelGGL((k_reduce_pass2<DT, true>), dim3(1), dim3(kFinalBlock), 0, (hipStream_t)L.stream,
                            (const double *)L.ws, n_tiles, L.result);
