@@ -43,19 +43,31 @@ def candidates(kind: str, n: int, dtype: int, cus: int):
 
 
 def time_config(fn, cfg, reps: int, warm: int = 2) -> float:
-    """Median event time (ms) of fn(cfg) over reps launches."""
+    """Device time (ms) per launch of fn(cfg): `reps` launches captured in one
+    HIP graph, replayed three times between two events, median. Back-to-back
+    launches without Python or host launch overhead, which at small sizes
+    would otherwise hide the device time the knobs change."""
     import torch
 
     for _ in range(warm):
         fn(cfg)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for a, b in ev:
-        a.record()
-        fn(cfg)
-        b.record()
     torch.cuda.synchronize()
-    ts = sorted(a.elapsed_time(b) for a, b in ev)
-    return ts[len(ts) // 2]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn(cfg)
+    g.replay()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) / reps)
+    del g
+    return sorted(ts)[1]
 
 
 # Representative programs outside the catalogue: they run on the interpreter
