@@ -84,7 +84,10 @@ __device__ __forceinline__ void batch_tile(const void *const (&op)[NL], const ty
         for (int q = 0; q < E::n_loads; ++q) rin[q] = rsrc((const S *)op[q] + t * T, whole * 16);
         if (out) rout = rsrc((S *)out + t * T, whole * 16);
     }
-#pragma unroll
+    // Bursts are not unrolled: unrolled, the compiler hoisted the next
+    // burst's loads and the kernel needed 240 registers instead of 147 (FP32,
+    // 3 operands, 8 chunks), for no gain.
+#pragma unroll 1
     for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
         u32x4 raw[NL][UR];
 #pragma unroll
