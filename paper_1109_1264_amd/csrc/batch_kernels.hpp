@@ -86,7 +86,7 @@ __device__ __forceinline__ void batch_tile(const void *const (&op)[NL], const ty
     }
     // Bursts are not unrolled: unrolled, the compiler hoisted the next
     // burst's loads and the kernel needed 240 registers instead of 147 (FP32,
-    // 3 operands, 8 chunks), for no gain.
+    // 3 operands, 8 chunks) while running 1-3% slower.
 #pragma unroll 1
     for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
         u32x4 raw[NL][UR];
