@@ -163,3 +163,22 @@ def test_item_with_more_partials_than_combine_lanes():
         r = S.salt_dot(it["operands"][0], it["operands"][1])
         torch.cuda.synchronize()
         assert float(r.item()) == float(it["dot_out"].item()), it["n"]
+
+
+def test_c4_full_size():
+    """The batched workload at its full size: 4096 instances, lognormal
+    lengths (median 4096, clipped 64..2^20, about 50.6 M elements), FP32,
+    alpha_k a_k + (b_k - c_k) and dot(a_k, b_k), one graph launch with the
+    tuned knobs; every output bit-exact and every dot within tolerance of the
+    oracle, and every dot with the bits of the same item run alone."""
+    dtype = "f32"
+    lengths = [int(v) for v in workloads.batch_lengths(4096, seed=workloads.SEED_BATCHED)]
+    assert 50_000_000 < sum(lengths) < 51_000_000
+    items, host = make_batch(dtype, lengths, workloads.SEED_BATCHED)
+    b = Batch(ABC, items, CODE[dtype])
+    g = b.graph()
+    print("c4 full size: %d items, %d elements" % (len(items), sum(lengths)), flush=True)
+    g.launch()
+    check(items, host, dtype, alone_dot=True)
+    g.close()
+    b.close()

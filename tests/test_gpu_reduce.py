@@ -125,3 +125,18 @@ def test_deterministic_across_repeats_shapes_and_alignment(dtype):
     r2 = gpu_nrm2(dx)
     assert gpu_nrm2(to_dev(x, dtype, offset=5)) == r2
     assert gpu_nrm2(dx, config=(16, 1, 7)) == r2
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_precision_workload_full_size(dtype):
+    """The precision workload at its full size: n = 2^26, random signs,
+    log10|x| ~ U[-4, 4] (seed 3000), stored with round-to-nearest-even;
+    dot and nrm2 within the tolerance of the oracle's Dot2 on the stored
+    values."""
+    n = 1 << 26
+    x64, y64 = workloads.ill_conditioned(n, workloads.SEED_PRECISION)
+    x, y = workloads.store(x64, dtype), workloads.store(y64, dtype)
+    dx, dy = to_dev(x, dtype), to_dev(y, dtype)
+    print("precision workload", dtype, n, flush=True)
+    check_dot(dtype, x, y, gpu_dot(dx, dy))
+    check_nrm2(dtype, x, gpu_nrm2(dx))
