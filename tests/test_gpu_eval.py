@@ -214,3 +214,17 @@ def test_closed_form():
     S.salt_eval(prog, [to_dev(i, "f64"), to_dev(2 * i, "f64"), to_dev(i, "f64")], [], out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), 2 * i)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_programs_without_operands(dtype):
+    """Trees of scalars only (no vector operand): every element is the same
+    rounded value; aligned and unaligned outputs, ragged lengths."""
+    T = S.token
+    progs = [[T(S.SCALAR, 0)],
+             [T(S.SCALAR, 0), T(S.SCALAR, 1), T(S.MUL)],
+             [T(S.SCALAR, 1), T(S.SCALAR, 0), T(S.SUB), T(S.SCALAR, 2), T(S.ADD)]]
+    for k, prog in enumerate(progs):
+        for n in (1, 1000, 100003):
+            for offset in (0, 1):
+                run_case(prog, dtype, n, 7000 + k, offset=offset, scalars=[0.1, -3.75, 1e-3])
