@@ -84,11 +84,18 @@ __device__ __forceinline__ void batch_tile(const void *const (&op)[NL], const ty
         for (int q = 0; q < E::n_loads; ++q) rin[q] = rsrc((const S *)op[q] + t * T, whole * 16);
         if (out) rout = rsrc((S *)out + t * T, whole * 16);
     }
+    // Chunk rows (kBlock chunks each) that hold elements of the item. Rows
+    // past them would only read zeros and drop their stores, and adding the
+    // product +0 leaves an accumulator's bits unchanged (it is never -0), so
+    // a short last tile stops after its last burst with data.
+    const int rows = FORM == kWhole ? kChunksPerLane
+                                    : (int)(m < T ? (m + (int64_t)kBlock * V - 1) / ((int64_t)kBlock * V)
+                                                  : (int64_t)kChunksPerLane);
     // Bursts are not unrolled: unrolled, the compiler hoisted the next
     // burst's loads and the kernel needed 240 registers instead of 147 (FP32,
     // 3 operands, 8 chunks) while running 1-3% slower.
 #pragma unroll 1
-    for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
+    for (int it0 = 0; it0 < rows; it0 += UR) {
         u32x4 raw[NL][UR];
 #pragma unroll
         for (int q = 0; q < E::n_loads; ++q)

@@ -72,37 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pass1(RedArgs a) {
             rx = rsrc((const typename Tr<DT>::S *)a.x + t * T, whole * 16);
             ry = rsrc((const typename Tr<DT>::S *)(NRM ? a.x : a.y) + t * T, whole * 16);
         }
-#pragma unroll
-        for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
-            u32x4 xr[UR], yr[UR];
-            if (full) {
-#pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    xr[u] = ld16<NT>(x16 + c0 + (int64_t)(it0 + u) * kBlock);
-                    if constexpr (!NRM) yr[u] = ld16<NT>(y16 + c0 + (int64_t)(it0 + u) * kBlock);
-                }
-            } else if (ragged) {
-#pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    const int32_t off = ((it0 + u) * kBlock + (int32_t)threadIdx.x) * 16;
-                    xr[u] = bld16<NT>(rx, off);
-                    if constexpr (!NRM) yr[u] = bld16<NT>(ry, off);
-                }
-#pragma unroll
-                for (int u = 0; u < UR; ++u)
-                    if (straddle >= 0 && it0 + u == straddle / kBlock && (int)threadIdx.x == straddle % kBlock) {
-                        const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
-                        xr[u] = load_chunk_guarded<DT, NT>(a.x, ci, a.n, false);
-                        if constexpr (!NRM) yr[u] = load_chunk_guarded<DT, NT>(a.y, ci, a.n, false);
-                    }
-            } else {
-#pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
-                    xr[u] = load_chunk_guarded<DT, NT>(a.x, ci, a.n, a.vec);
-                    if constexpr (!NRM) yr[u] = load_chunk_guarded<DT, NT>(a.y, ci, a.n, a.vec);
-                }
-            }
+        const auto accumulate = [&](const u32x4 (&xr)[UR], const u32x4 (&yr)[UR]) {
 #pragma unroll
             for (int u = 0; u < UR; ++u)
 #pragma unroll
@@ -110,6 +80,63 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pass1(RedArgs a) {
                     const auto xv = Tr<DT>::get(xr[u], p);
                     acc_add<DT, MODE>(acc[p], xv, NRM ? xv : Tr<DT>::get(yr[u], p));
                 }
+        };
+        if (full) {
+#pragma unroll
+            for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
+                u32x4 xr[UR], yr[UR];
+#pragma unroll
+                for (int u = 0; u < UR; ++u) {
+                    xr[u] = ld16<NT>(x16 + c0 + (int64_t)(it0 + u) * kBlock);
+                    if constexpr (!NRM) yr[u] = ld16<NT>(y16 + c0 + (int64_t)(it0 + u) * kBlock);
+                }
+                accumulate(xr, yr);
+            }
+        } else {
+            // Chunk rows (kBlock chunks each) that hold elements: rows past
+            // them would only add the product +0, which leaves an
+            // accumulator's bits unchanged (it is never -0), so a short tile
+            // neither loads nor adds them. A burst issues all its rows'
+            // loads before it adds any.
+            const int rows = m < T ? (int)((m + (int64_t)kBlock * V - 1) / ((int64_t)kBlock * V)) : kChunksPerLane;
+            const u32x4 zero = {0u, 0u, 0u, 0u};
+#pragma unroll 1
+            for (int it0 = 0; it0 < rows; it0 += UR) {
+                u32x4 xr[UR], yr[UR];
+#pragma unroll
+                for (int u = 0; u < UR; ++u) {
+                    xr[u] = zero;
+                    if constexpr (!NRM) yr[u] = zero;
+                    if (it0 + u >= rows) continue;
+                    if (ragged) {
+                        const int32_t off = ((it0 + u) * kBlock + (int32_t)threadIdx.x) * 16;
+                        xr[u] = bld16<NT>(rx, off);
+                        if constexpr (!NRM) yr[u] = bld16<NT>(ry, off);
+                    } else {
+                        const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
+                        xr[u] = load_chunk_guarded<DT, NT>(a.x, ci, a.n, a.vec);
+                        if constexpr (!NRM) yr[u] = load_chunk_guarded<DT, NT>(a.y, ci, a.n, a.vec);
+                    }
+                }
+                if (ragged) {
+#pragma unroll
+                    for (int u = 0; u < UR; ++u)
+                        if (straddle >= 0 && it0 + u == straddle / kBlock && (int)threadIdx.x == straddle % kBlock) {
+                            const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
+                            xr[u] = load_chunk_guarded<DT, NT>(a.x, ci, a.n, false);
+                            if constexpr (!NRM) yr[u] = load_chunk_guarded<DT, NT>(a.y, ci, a.n, false);
+                        }
+                }
+#pragma unroll
+                for (int u = 0; u < UR; ++u) {
+                    if (it0 + u >= rows) continue;
+#pragma unroll
+                    for (int p = 0; p < V; ++p) {
+                        const auto xv = Tr<DT>::get(xr[u], p);
+                        acc_add<DT, MODE>(acc[p], xv, NRM ? xv : Tr<DT>::get(yr[u], p));
+                    }
+                }
+            }
         }
         const double v = block_sum<kBlock / 64>(lane_value<DT>(acc), lds);
         if (threadIdx.x == 0) {
@@ -155,10 +182,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce_expr(RedExprArgs<DT> a, Inter
         Acc<DT> acc[V];
         const int64_t c0 = t * ((int64_t)kBlock * kChunksPerLane) + threadIdx.x;
         const bool full = t < n_full;
+        // A short tile stops after its last chunk row with data (the rows
+        // past it would add +0, which changes no accumulator's bits).
+        const int64_t m = a.n - t * T;
+        const int rows = m < T ? (int)((m + (int64_t)kBlock * V - 1) / ((int64_t)kBlock * V)) : kChunksPerLane;
         // One burst per iteration, not unrolled: the interpreter loop inside
         // would otherwise be copied per burst.
 #pragma unroll 1
-        for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
+        for (int it0 = 0; it0 < rows; it0 += UR) {
             u32x4 raw[NL][UR];
 #pragma unroll
             for (int k = 0; k < NL; ++k)
