@@ -82,6 +82,8 @@ def load(path: str) -> ctypes.CDLL:
     L.oracle_naive_dot_f64.restype = D
     L.oracle_naive_dot_f32.argtypes = [I64, P, P]
     L.oracle_naive_dot_f32.restype = ctypes.c_float
+    L.oracle_reduce_canonical.argtypes = [I, I, I64, P, P, P]
+    L.oracle_reduce_canonical.restype = I
     L.oracle_copy.argtypes = [I64, P, I64, P, I64, I]
     L.oracle_copy.restype = I
     L.oracle_iamax_f64.argtypes = [I64, P, I64]
@@ -214,6 +216,26 @@ def naive_dot(x: np.ndarray, y: np.ndarray, dtype: str = "f64") -> float:
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     return float(L.oracle_naive_dot_f64(len(x), _ptr(x), _ptr(y)))
+
+
+_KIND = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+MODES = {"dot": 0, "nrm2": 1, "asum": 2}
+
+
+def reduce_canonical(mode: str, x: np.ndarray, y: np.ndarray | None, dtype: str):
+    """dot / nrm2 / asum of stored values in the library's documented
+    summation order (tiles of 256 lanes x 16 chunks, per-slot accumulators,
+    butterflies, a 1024-lane combine; the order is a reading, since the
+    paper leaves it open). Returns np.float64 for binary64 storage, else
+    np.float32 -- the result type, for bit-for-bit comparison."""
+    x = np.ascontiguousarray(x, dtype=_NP[dtype])
+    yy = x if y is None else np.ascontiguousarray(y, dtype=_NP[dtype])
+    if mode == "dot" and len(yy) != len(x):
+        raise ValueError("length mismatch")
+    r = ctypes.c_double()
+    if lib().oracle_reduce_canonical(_KIND[dtype], MODES[mode], len(x), _ptr(x), _ptr(yy), ctypes.byref(r)):
+        raise ValueError("bad arguments")
+    return np.float64(r.value) if dtype == "f64" else np.float32(r.value)
 
 
 # ---------------------------------------------------------------------------

@@ -28,6 +28,13 @@
  *    sqrt(sum x_i^2), from Dot2(x, x).
  *  - oracle_naive_dot_*: plain sequential loops, kept as a CPU timing baseline
  *    and as the same-precision FP32 mode (not a reference value at large n).
+ *  - oracle_reduce_canonical: a second, bit-exact reduction oracle. The
+ *    paper's reduction keeps per-slot partial sums and ends with a
+ *    reduction step (Sec. 4.2) without fixing an order; the library fixes
+ *    one that depends on (n, storage type) only, so its results are
+ *    reproducible. This replays that documented order on the CPU, in the
+ *    same precisions, so dot, nrm2 and asum can be compared bit for bit
+ *    (the order is a reading of the paper, written out below).
  *  - oracle_copy, oracle_iamax_*: the BLAS level-1 interface that the paper
  *    measures against (Sec. 1, the BLAS interface; Sec. 5, the xDOT / xSCAL /
  *    xAXPY / xCOPY comparisons), with its strided vectors. A BLAS vector of n
@@ -283,6 +290,122 @@ float oracle_naive_dot_f32(int64_t n, const float *x, const float *y) {
     float s = 0.0f;
     for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];
     return s;
+}
+
+/* ---- the canonical summation order (second reduction oracle) -------------- */
+
+/* The order, for storage type k with V = 16 / (element bytes) elements per
+ * 16-byte chunk (V = 2, 4, 8 for binary64, binary32, 16-bit):
+ *  1. tiles of T = 256 * 16 * V elements; elements past n read as zero;
+ *  2. in tile t, "lane" l (0..255) visits chunks 16*256*t + 256*j + l for
+ *     j = 0..15 in that order, and element p of a chunk (index chunk*V + p)
+ *     goes to its slot p;
+ *  3. a slot accumulates, for binary64, s = fma(x, y, s); for binary32,
+ *     compensated binary32: p = x*y with its exact error fma(x, y, -p),
+ *     TwoSum(s, p) -> (s, e), c = c + (e + product error); for 16-bit
+ *     storage (exact binary32 products) TwoSum(s, x*y) -> (s, e), c = c + e;
+ *     a slot's value is s (binary64) or (double)s + (double)c;
+ *  4. the lane's value is the binary64 sum of its slot values in slot order;
+ *  5. lanes form 4 groups of 64; a group is summed by a butterfly: for
+ *     d = 1, 2, 4, ..., 32, every member i becomes v_i + v_(i xor d); the
+ *     tile's partial is (g0 + g1) + (g2 + g3);
+ *  6. the partials are combined by 1024 "lanes": lane l adds partials l,
+ *     l + 1024, ... in order (from +0), the 16 groups of 64 lanes are summed
+ *     by the same butterfly, and the 16 group sums by a pairwise tree
+ *     (pairs (0,1), (2,3), ... then pairs of those, ...);
+ *  7. nrm2 takes the square root; the result is rounded once to binary32
+ *     for every storage type but binary64.
+ * The value added per element is x*y (dot), x*x (nrm2) or |x|*1 (asum). */
+
+#define RC_LANES 256
+#define RC_CHUNKS 16
+#define RC_FINAL 1024
+
+static double rc_butterfly64(const double *v0) {
+    double v[64], t[64];
+    memcpy(v, v0, sizeof v);
+    for (int d = 1; d < 64; d <<= 1) {
+        for (int i = 0; i < 64; ++i) t[i] = v[i] + v[i ^ d];
+        memcpy(v, t, sizeof v);
+    }
+    return v[0];
+}
+
+static void rc_two_sum_f(float a, float b, float *s, float *e) {
+    *s = a + b;
+    float z = *s - a;
+    *e = (a - (*s - z)) + (b - z);
+}
+
+/* element i of a kind-k array as binary32 (kinds 1-3) */
+static float rc_elem_f(int kind, const void *p, int64_t i) {
+    if (kind == 1) return ((const float *)p)[i];
+    uint16_t h = ((const uint16_t *)p)[i];
+    return kind == 2 ? oracle_bf16_to_f32(h) : oracle_f16_to_f32(h);
+}
+
+static double rc_tile(int kind, int mode, int64_t n, const void *x, const void *y, int64_t t) {
+    const int V = kind == 0 ? 2 : kind == 1 ? 4 : 8;
+    double lane[RC_LANES];
+    for (int l = 0; l < RC_LANES; ++l) {
+        double sd[8];
+        float sf[8], cf[8];
+        for (int p = 0; p < 8; ++p) sd[p] = 0.0, sf[p] = 0.0f, cf[p] = 0.0f;
+        for (int j = 0; j < RC_CHUNKS; ++j) {
+            const int64_t chunk = t * RC_LANES * RC_CHUNKS + (int64_t)j * RC_LANES + l;
+            for (int p = 0; p < V; ++p) {
+                const int64_t i = chunk * V + p;
+                if (kind == 0) {
+                    double a = i < n ? ((const double *)x)[i] : 0.0, b;
+                    if (mode == 0) b = i < n ? ((const double *)y)[i] : 0.0;
+                    else if (mode == 1) b = a;
+                    else a = fabs(a), b = 1.0;
+                    sd[p] = fma(a, b, sd[p]);
+                } else {
+                    float a = i < n ? rc_elem_f(kind, x, i) : 0.0f, b, e;
+                    if (mode == 0) b = i < n ? rc_elem_f(kind, y, i) : 0.0f;
+                    else if (mode == 1) b = a;
+                    else a = fabsf(a), b = 1.0f;
+                    const float prod = a * b;
+                    rc_two_sum_f(sf[p], prod, &sf[p], &e);
+                    if (kind == 1) cf[p] = cf[p] + (e + fmaf(a, b, -prod));
+                    else cf[p] = cf[p] + e;
+                }
+            }
+        }
+        double v = 0.0;
+        for (int p = 0; p < V; ++p) {
+            const double slot = kind == 0 ? sd[p] : (double)sf[p] + (double)cf[p];
+            v = p == 0 ? slot : v + slot;
+        }
+        lane[l] = v;
+    }
+    double g[4];
+    for (int k = 0; k < 4; ++k) g[k] = rc_butterfly64(lane + 64 * k);
+    return (g[0] + g[1]) + (g[2] + g[3]);
+}
+
+/* kind: 0 binary64, 1 binary32, 2 bfloat16, 3 binary16 (raw bits);
+ * mode: 0 dot, 1 nrm2, 2 asum (y unused for 1 and 2). The result is
+ * written as binary64 (kind 0) or as the binary32 value widened. */
+int oracle_reduce_canonical(int kind, int mode, int64_t n, const void *x, const void *y, double *result) {
+    if (kind < 0 || kind > 3 || mode < 0 || mode > 2 || n < 0 || !result) return 1;
+    const int V = kind == 0 ? 2 : kind == 1 ? 4 : 8;
+    const int64_t T = (int64_t)RC_LANES * RC_CHUNKS * V;
+    const int64_t P = (n + T - 1) / T;
+    double fin[RC_FINAL];
+    for (int l = 0; l < RC_FINAL; ++l) fin[l] = 0.0;
+    /* partials are produced in tile order and folded straight into lane
+     * (tile mod 1024), which is the order lane l adds them in */
+    for (int64_t t = 0; t < P; ++t) fin[t % RC_FINAL] = fin[t % RC_FINAL] + rc_tile(kind, mode, n, x, y, t);
+    double g[RC_FINAL / 64];
+    for (int k = 0; k < RC_FINAL / 64; ++k) g[k] = rc_butterfly64(fin + 64 * k);
+    for (int h = RC_FINAL / 128; h >= 1; h >>= 1)
+        for (int k = 0; k < h; ++k) g[k] = g[2 * k] + g[2 * k + 1];
+    double r = g[0];
+    if (mode == 1) r = sqrt(r);
+    *result = kind == 0 ? r : (double)(float)r;
+    return 0;
 }
 
 /* ---- BLAS level-1 with increments ------------------------------------------ */

@@ -60,6 +60,21 @@ MUTANTS = {
     "iamax_signed_f32": ("const float a = fabsf(x[i * inc]);", "const float a = x[i * inc];"),
     # iamax ignoring the increment
     "iamax_unit_stride": ("const double a = fabs(x[i * inc]);", "const double a = fabs(x[i]);"),
+    # canonical order: a lane taking 16 consecutive chunks instead of every 256th
+    "rc_lane_contiguous": ("(int64_t)j * RC_LANES + l;", "(int64_t)l * RC_CHUNKS + j;"),
+    # canonical order: the four lane groups summed sequentially
+    "rc_groups_sequential": ("return (g[0] + g[1]) + (g[2] + g[3]);", "return ((g[0] + g[1]) + g[2]) + g[3];"),
+    # canonical order: the final tree pairing k with k + h
+    "rc_final_tree_pairs": ("for (int k = 0; k < h; ++k) g[k] = g[2 * k] + g[2 * k + 1];",
+                            "for (int k = 0; k < h; ++k) g[k] = g[k] + g[k + h];"),
+    # canonical order: binary32 compensation without the sum's error
+    "rc_drop_sum_error": ("if (kind == 1) cf[p] = cf[p] + (e + fmaf(a, b, -prod));",
+                          "if (kind == 1) cf[p] = cf[p] + fmaf(a, b, -prod);"),
+    # canonical order: nrm2 without its square root
+    "rc_nrm2_no_sqrt": ("if (mode == 1) r = sqrt(r);", "if (mode == 1) r = r;"),
+    # canonical order: elements past n read instead of zero (binary64)
+    "rc_tail_read": ("double a = i < n ? ((const double *)x)[i] : 0.0, b;",
+                     "double a = i < n ? ((const double *)x)[i] : 1.0, b;"),
 }
 
 

@@ -18,7 +18,9 @@ Pins used (none retypes the oracle's own loops):
   cases for the 16-bit storage formats;
 - numpy slicing for BLAS strided vectors (x[::inc], reversed for inc < 0),
   numpy ``argmax`` (first occurrence) and hand-worked NaN / tie cases for
-  iamax, and ``math.fsum`` for asum.
+  iamax, and ``math.fsum`` for asum;
+- for the replay of the library's summation order: hand-worked inputs whose
+  result depends on that order, exact integer sums and the Dot2 bound.
 """
 from __future__ import annotations
 
@@ -424,6 +426,87 @@ def check_asum(o):
         assert abs(got - exact) <= dot2_bound(n, exact, exact), (n, got, exact)
 
 
+def check_reduce_canonical(o):
+    """The replay of the library's summation order (a reading: the paper
+    leaves the order open). Pins: hand-worked inputs whose result depends on
+    the order -- each value below is derived by hand from the order's
+    definition (tiles of 256 lanes x 16 chunks x V elements, lane l taking
+    chunks l, l+256, ...; slot p per element of a chunk; butterflies over 64
+    lanes; (g0 + g1) + (g2 + g3); a pairwise tree over the final combine's
+    16 groups) and differs from what a sequential sum gives --, exact
+    integer sums (exact in any order), and the Dot2 bound on random data."""
+    big = 2.0 ** 53
+    T64 = 256 * 16 * 2
+
+    def dot64(x):
+        return float(o.reduce_canonical("dot", x, np.ones(len(x)), "f64"))
+
+    # slot separation and the lane's chunk stride: elements 0 and 512 are
+    # lane 0's chunks 0 and 256 (slot 0), element 1 is slot 1: the slot-0 sum
+    # 2^60 - 2^60 is exact and the slot-1 value 1 survives (sequentially the
+    # 1 would be lost in 2^60 + 1)
+    x = np.zeros(T64)
+    x[0], x[1], x[512] = 2.0 ** 60, 1.0, -(2.0 ** 60)
+    assert dot64(x) == 1.0
+    assert o.naive_dot(x, np.ones(T64)) == 0.0
+    # butterfly inside a group of 64 lanes: lanes 0, 2, 3 hold 2^53, 1, 1
+    # (elements 0, 4, 6): (v0 + v1) + (v2 + v3) = 2^53 + 2; sequential 2^53
+    x = np.zeros(T64)
+    x[0], x[4], x[6] = big, 1.0, 1.0
+    assert dot64(x) == big + 2
+    # the four groups: lanes 0, 128, 192 -> (g0 + g1) + (g2 + g3) = 2^53 + 2
+    x = np.zeros(T64)
+    x[0], x[256], x[384] = big, 1.0, 1.0
+    assert dot64(x) == big + 2
+    # the final combine's butterfly: tiles 0, 2, 3 (its lanes 0, 2, 3)
+    x = np.zeros(4 * T64)
+    x[0], x[2 * T64], x[3 * T64] = big, 1.0, 1.0
+    assert dot64(x) == big + 2
+    # the final combine's pairwise tree over its 16 groups: tiles 0, 128,
+    # 192 sit in groups 0, 2, 3 -> (g0 + g1) + (g2 + g3) = 2^53 + 2
+    x = np.zeros(193 * T64)
+    x[0], x[128 * T64], x[192 * T64] = big, 1.0, 1.0
+    assert dot64(x) == big + 2
+    # compensated binary32 slots keep the 1 that 2^30 + 1 rounds away (one
+    # slot: elements 0, 1024, 2048 are lane 0's chunks 0, 256, 512, slot 0)
+    for dt, hi, lo in (("f32", 2.0 ** 30, 1.0), ("bf16", 2.0 ** 30, 1.0), ("f16", 2.0 ** 15, 2.0 ** -9)):
+        V = 4 if dt == "f32" else 8
+        xs = np.zeros(256 * 16 * V, np.float32)
+        xs[0], xs[256 * V], xs[512 * V] = hi, lo, -hi
+        xs = xs if dt == "f32" else o.narrow(xs, dt)
+        ones = np.ones(len(xs), np.float32)
+        ones = ones if dt == "f32" else o.narrow(ones, dt)
+        assert float(o.reduce_canonical("dot", xs, ones, dt)) == lo, dt
+    # exact integer sums, every type, mode and a ragged tail
+    for dt, V in (("f64", 2), ("f32", 4), ("bf16", 8), ("f16", 8)):
+        T = 256 * 16 * V
+        for n in (0, 1, 5, T - 1, T + 1, 3 * T + 5):
+            i = np.arange(n, dtype=np.int64)
+            xi, yi = i % 7 - 3, i % 5 - 2
+            xs = xi.astype(np.float64) if dt == "f64" else xi.astype(np.float32)
+            ys = yi.astype(np.float64) if dt == "f64" else yi.astype(np.float32)
+            if dt in ("bf16", "f16"):
+                xs, ys = o.narrow(xs, dt), o.narrow(ys, dt)
+            rt = np.float64 if dt == "f64" else np.float32
+            assert o.reduce_canonical("dot", xs, ys, dt) == rt(int((xi * yi).sum())), (dt, n)
+            assert o.reduce_canonical("asum", xs, None, dt) == rt(int(np.abs(xi).sum())), (dt, n)
+            assert o.reduce_canonical("nrm2", xs, None, dt) == rt(math.sqrt(int((xi * xi).sum()))), (dt, n)
+        ones = np.ones(4 ** 8, np.float64 if dt == "f64" else np.float32)
+        ones = ones if dt in ("f64", "f32") else o.narrow(ones, dt)
+        assert float(o.reduce_canonical("nrm2", ones, None, dt)) == 256.0, dt
+    # random values: within the tolerance of Dot2 on the stored values
+    for dt, V in (("f64", 2), ("f32", 4), ("bf16", 8), ("f16", 8)):
+        n = 3 * 256 * 16 * V + 17
+        xs, ys = workloads.uniform(n, dt, 77, 2)
+        xw, yw = o.widen(xs, dt), o.widen(ys, dt)
+        ref, sabs = o.dot2(xw, yw)
+        assert abs(float(o.reduce_canonical("dot", xs, ys, dt)) - ref) <= o.TOL[dt] * sabs, dt
+        nref = o.nrm2(xw)
+        assert abs(float(o.reduce_canonical("nrm2", xs, None, dt)) - nref) <= o.TOL[dt] * nref, dt
+        aref = math.fsum(np.abs(xw).tolist())
+        assert abs(float(o.reduce_canonical("asum", xs, None, dt)) - aref) <= o.TOL[dt] * aref, dt
+
+
 def check_iamax(o):
     """iamax against numpy argmax of |x| (first occurrence of the maximum) and
     hand-worked cases: ties, NaNs, strides, empty vectors."""
@@ -476,6 +559,7 @@ CHECKS = {
     "scal_axpy_strided": check_scal_axpy_strided,
     "asum": check_asum,
     "iamax": check_iamax,
+    "reduce_canonical": check_reduce_canonical,
 }
 
 
