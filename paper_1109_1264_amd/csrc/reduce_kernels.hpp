@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_expr(RedExprArgs<DT> a, Inter
                 xs[j] = Tr<DT>::round(NRM ? tos[j] : stack[j * kBlock + threadIdx.x]);
                 ys[j] = Tr<DT>::round(tos[j]);
             }
-            if (!full) {
+            if (__builtin_expect(!full, 0)) {
 #pragma unroll
                 for (int u = 0; u < UR; ++u)
 #pragma unroll
