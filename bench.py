@@ -15,7 +15,9 @@ The same JSON line also reports the whole size sweep and the three systems
 layers beside the plain binary64 kernels (each measured after the timed
 step):
     sweep:     axpy, dot, nrm2 and the 5-operand tree for n = 2^10 .. 2^28 in
-               binary64 and binary32 (device time per launch, GB/s);
+               binary64 and binary32 (device time per launch, GB/s, % of
+               8 TB/s, % of the copy tree's rate at the same n, and whether
+               the working set is past the last-level cache);
     fusion:    one fused pass against the same result composed from
                single-operation calls (out-of-place scale, a + (b - c),
                dot of two trees), with identical bits;
@@ -312,21 +314,32 @@ def section_sweep(args):
         d = torch.empty(1 << hi, dtype=a.dtype, device="cuda")
         ws = salt.workspace(1 << hi, code)
         r = torch.empty(1, dtype=torch.float64 if name == "f64" else torch.float32, device="cuda")
-        rows = {"axpy": [], "dot": [], "nrm2": [], "tree5": []}
+        copy = [T(salt.LOAD, 0)]
+        rows = {"axpy": [], "dot": [], "nrm2": [], "tree5": [], "copy": []}
         for l in range(10, hi + 1):
             n = 1 << l
             al = workloads.alpha(workloads.sweep_seed(n))
             v = [t[:n] for t in (a, b, c, e, f)]
             dn = d[:n]
-            fns = {"axpy": (lambda: salt.salt_axpy(al, v[0], dn), 3),
+            fns = {"copy": (lambda: salt.salt_eval(copy, v[:1], [], dn), 2),
+                   "axpy": (lambda: salt.salt_axpy(al, v[0], dn), 3),
                    "dot": (lambda: salt.salt_dot(v[0], v[1], result=r, ws=ws), 2),
                    "nrm2": (lambda: salt.salt_nrm2(v[2], result=r, ws=ws), 1),
                    "tree5": (lambda: salt.salt_eval(tree5, v, [], dn), 6)}
             reps = 50 if l <= 20 else (10 if l <= 24 else 4)
+            copy_gbps = None
             for k, (fn, arrays) in fns.items():
                 t = graph_ms(fn, reps)
-                rows[k].append([l, round(t, 5), round(arrays * es * n / (t * 1e-3) / 1e9, 1)])
-        out[name] = {k: {"columns": ["log2n", "ms", "GBps"], "rows": v} for k, v in rows.items()}
+                nbytes = arrays * es * n
+                gbps = nbytes / (t * 1e-3) / 1e9
+                if k == "copy":
+                    copy_gbps = gbps
+                # % of HBM peak is meaningful only once the working set is well
+                # past the 256 MiB last-level cache (>= 1 GiB)
+                rows[k].append([l, round(t, 5), round(gbps, 1), round(100 * gbps / 8000, 1),
+                                round(100 * gbps / copy_gbps, 1), nbytes >= (1 << 30)])
+        out[name] = {k: {"columns": ["log2n", "ms", "GBps", "pct_of_8TBps", "pct_of_copy_same_n", "hbm_regime"],
+                         "rows": v} for k, v in rows.items()}
         del a, b, c, e, f, d, ws
         torch.cuda.empty_cache()
     return out
