@@ -121,7 +121,21 @@ def cpu_baseline(log2n_sample: int, reps: int = 12):
             "sample": "one step of the same hot path (tree eval, axpy, Dot2 dot, Dot2 nrm2) on n=2^%d "
                       "binary64 elements (of the 2^28 in the GPU step), median of %d runs, "
                       "single-threaded plain C" % (log2n_sample, reps),
-            "seconds_per_step": round(t, 4)}
+            "seconds_per_step": round(t, 4), "host": host_cpu()}
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and logical CPU count (the baseline's machine)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
 # ---------------------------------------------------------------------------
