@@ -97,11 +97,16 @@ __device__ __forceinline__ void batch_tile(const void *const (&op)[NL], const ty
 #pragma unroll 1
     for (int it0 = 0; it0 < rows; it0 += UR) {
         u32x4 raw[NL][UR];
+        // a row of a short tile past its last element is neither loaded nor
+        // stored nor added (uniform test)
+        const auto live = [&](int u) { return FORM == kWhole || it0 + u < rows; };
 #pragma unroll
         for (int q = 0; q < E::n_loads; ++q)
 #pragma unroll
             for (int u = 0; u < UR; ++u) {
                 const int64_t ci = c0 + (int64_t)(it0 + u) * kBlock;
+                raw[q][u] = u32x4{0u, 0u, 0u, 0u};
+                if (!live(u)) continue;
                 if constexpr (FORM == kWhole) {
                     raw[q][u] = gld16<NT>(op[q], ci);
                 } else if constexpr (FORM == kRagged) {
@@ -124,6 +129,7 @@ __device__ __forceinline__ void batch_tile(const void *const (&op)[NL], const ty
         if (out) {
 #pragma unroll
             for (int u = 0; u < UR; ++u) {
+                if (!live(u)) continue;
                 C r[V];
 #pragma unroll
                 for (int p = 0; p < V; ++p) r[p] = E::ev(BChunkCtx<DT, NL, UR, NS>{raw, s, u, p});
@@ -146,9 +152,11 @@ __device__ __forceinline__ void batch_tile(const void *const (&op)[NL], const ty
         }
         if constexpr (DOT) {
 #pragma unroll
-            for (int u = 0; u < UR; ++u)
+            for (int u = 0; u < UR; ++u) {
+                if (!live(u)) continue;
 #pragma unroll
                 for (int p = 0; p < V; ++p) acc[p].add(Tr<DT>::get(raw[0][u], p), Tr<DT>::get(raw[1][u], p));
+            }
         }
     }
 }
