@@ -20,7 +20,8 @@ step):
                the working set is past the last-level cache);
     fusion:    one fused pass against the same result composed from
                single-operation calls (out-of-place scale, a + (b - c),
-               dot of two trees), with identical bits;
+               dot of two trees), with identical bits; and the Fig. 1 tree
+               at n = 2^20 (cache-resident and with rotated buffers);
     precision: dot / nrm2 at n = 2^26, storage FP64 / FP32 / BF16, with the
                error against the binary64 oracle per result;
     blas1:     asum, iamax, scal and the strided routines at increments 2, 4;
@@ -419,7 +420,42 @@ def section_fusion(args):
                      "same_bits": same}
     del a, b, c, e, d, t, ws
     torch.cuda.empty_cache()
+    out["fig1_n2p20"] = fig1_small()
     return out
+
+
+def fig1_small() -> dict:
+    """The Fig. 1 tree d = a + (b - c) at its own size (binary64, n = 2^20,
+    32 MiB moved per launch): with the same buffers every launch (they stay
+    in the 256 MiB last-level cache) and with 16 buffer sets cycled (512 MiB,
+    so each launch streams from HBM)."""
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    T = salt.token
+    fig1 = [T(salt.LOAD, 0), T(salt.LOAD, 1), T(salt.LOAD, 2), T(salt.SUB), T(salt.ADD)]
+    n, sets = 1 << 20, 16
+    bufs = [workloads.uniform_device(n, "f64", workloads.SEED_FIG1 + k, 3) for k in range(sets)]
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(sets)]
+    t_res = graph_ms(lambda: salt.salt_eval(fig1, bufs[0], [], outs[0]), 64)
+    state = {"k": 0}
+
+    def rotated():
+        k = state["k"] % sets
+        state["k"] += 1
+        salt.salt_eval(fig1, bufs[k], [], outs[k])
+    t_rot = graph_ms(rotated, 64)
+    nbytes = 32 * n
+    del bufs, outs
+    torch.cuda.empty_cache()
+    return {"n": n, "dtype": "f64", "bytes_per_launch": nbytes,
+            "resident_ms": round(t_res, 5), "resident_GBps": round(nbytes / (t_res * 1e-3) / 1e9, 1),
+            "rotated_ms": round(t_rot, 5), "rotated_GBps": round(nbytes / (t_rot * 1e-3) / 1e9, 1),
+            "rotated_pct_of_8TBps": round(100 * nbytes / (t_rot * 1e-3) / 8e12, 1),
+            "rotation": "%d buffer sets (%d MiB) cycled launch by launch, beyond the last-level cache"
+                        % (sets, sets * nbytes >> 20)}
 
 
 # ---------------------------------------------------------------------------
