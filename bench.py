@@ -691,7 +691,7 @@ def main() -> int:
                          "each, and print nothing (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(element-wise work shards by index range and dot/nrm2 need one 8-byte "
               "combine; see the design notes). Run with --gpus 1.", file=sys.stderr)
         return 2

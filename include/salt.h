@@ -47,7 +47,7 @@ typedef enum {
     SALT_OK = 0,
     SALT_ERR_ARG = 1,         /* null pointer, bad length, bad dtype, overlap */
     SALT_ERR_PROGRAM = 2,     /* malformed postfix program                     */
-    SALT_ERR_UNSUPPORTED = 3, /* valid request outside this build's limits     */
+    SALT_ERR_UNSUPPORTED = 3, /* valid request outside the library's limits    */
     SALT_ERR_WORKSPACE = 4,   /* workspace missing, misaligned or too small    */
     SALT_ERR_DEVICE = 5       /* HIP reported an error                         */
 } salt_status;
