@@ -1,0 +1,46 @@
+"""The benchmark's command-line contract and its CPU-baseline leg, on the CPU:
+more than one GPU is refused with a message and exit status 2, and the
+baseline record names its unit, the threads it used and the host."""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout.strip() == ""
+
+
+def test_cpu_baseline_record():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    rec = bench.cpu_baseline(12, reps=1)
+    assert rec["kind"] == "oracle" and rec["unit"] == "GB/s" and rec["cores"] == 1
+    assert rec["value"] > 0 and rec["seconds_per_step"] > 0
+    assert "n=2^12" in rec["sample"]
+    assert rec["host"]["logical_cpus"] == os.cpu_count()
+    json.dumps(rec)  # one JSON line
+
+
+def test_traffic_only_for_the_profiled_kernel_source():
+    """The counter-derived traffic is reported only while the committed
+    counter summary was taken on the current tree-kernel source."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    with open(bench.PROFILE_PMC) as fh:
+        prof = json.load(fh)
+    got = bench.traffic_from_profile(prof["n"])
+    if prof["kernel_source_hash"] == bench.kernel_source_hash():
+        assert got == prof["traffic_bytes_per_launch"]
+    else:
+        assert got is None
