@@ -250,8 +250,9 @@ def section_main(args, out):
 
 
 def main_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5):
-    """Sampled bit-exact check of the tree kernel and full-length tolerance
-    checks of dot / nrm2 against the oracle, at the benchmarked size."""
+    """Sampled bit-exact check of the tree kernel, and full-length checks of
+    dot / nrm2 against the oracle (tolerance of Dot2, and bit for bit against
+    the replay of the summation order), at the benchmarked size."""
     import numpy as np
     import torch
 
@@ -275,9 +276,13 @@ def main_parity(n, a, b, c, e, f, d, r_dot, r_nrm, ws, tree5):
     dot_err = abs(float(r_dot.item()) - ref) / abs_sum
     nref = oracle.nrm2(ch)
     nrm_err = abs(float(r_nrm.item()) - nref) / nref
+    # bit for bit against the oracle's replay of the fixed summation order
+    dot_bits = float(r_dot.item()) == float(oracle.reduce_canonical("dot", ah, bh, "f64"))
+    nrm_bits = float(r_nrm.item()) == float(oracle.reduce_canonical("nrm2", ch, None, "f64"))
     return {"tree5_sampled_bit_exact": eval_ok, "samples": int(len(idx)),
             "dot_rel_err": dot_err, "nrm2_rel_err": nrm_err, "tol": 1e-13,
-            "ok": bool(eval_ok and dot_err <= 1e-13 and nrm_err <= 1e-13)}
+            "dot_bits_equal_order_replay": dot_bits, "nrm2_bits_equal_order_replay": nrm_bits,
+            "ok": bool(eval_ok and dot_err <= 1e-13 and nrm_err <= 1e-13 and dot_bits and nrm_bits)}
 
 
 # ---------------------------------------------------------------------------
