@@ -136,21 +136,26 @@ __device__ __forceinline__ void bst16(__amdgpu_buffer_rsrc_t r, int32_t off, u32
 }
 
 // Final combine over `count` partials by one workgroup of kFinalBlock lanes:
-// lane l adds partials l, l + 1024, l + 2048, ... in that order (loaded 8 at
-// a time), then block_sum. The value is returned in every thread.
+// lane l adds partials l, l + 1024, l + 2048, ... in that order, then
+// block_sum. The value is returned in every thread. Loads are issued 32 at a
+// time (one round trip for up to 32768 partials, i.e. 2^28 binary64
+// elements); slots past `count` add +0, which leaves the sum's bits
+// unchanged (it starts at +0 and is never -0).
 constexpr int kFinalBlock = 1024;
 
 __device__ __forceinline__ double combine_partials(const double *part, int64_t count, double *lds) {
+    constexpr int kBurst = 32;
     double v = 0.0;
-    int64_t i = threadIdx.x;
-    for (; i + 7 * kFinalBlock < count; i += 8 * kFinalBlock) {
-        double q[8];
+    for (int64_t base = threadIdx.x; base < count; base += (int64_t)kBurst * kFinalBlock) {
+        double q[kBurst];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) q[j] = part[i + j * kFinalBlock];
+        for (int j = 0; j < kBurst; ++j) {
+            const int64_t i = base + (int64_t)j * kFinalBlock;
+            q[j] = i < count ? part[i] : 0.0;
+        }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v = v + q[j];
+        for (int j = 0; j < kBurst; ++j) v = v + q[j];
     }
-    for (; i < count; i += kFinalBlock) v = v + part[i];
     return block_sum<kFinalBlock / 64>(v, lds);
 }
 
