@@ -81,10 +81,14 @@ EXPR_Q = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.SUB)]                              
 class Workload:
     """Device buffers for one (kind, tree, dtype) at the largest size swept."""
 
-    def __init__(self, kind: str, tree: str | None, dtype: int, n_max: int):
+    def __init__(self, kind: str, tree: str | None, dtype: int, n_max: int, rotate: bool = False):
         import torch
 
-        self.kind, self.dtype = kind, dtype
+        if rotate:
+            # at least 1 GiB per buffer, so that sizes below it have disjoint
+            # slices to rotate through (see sets())
+            n_max = max(n_max, (1 << 30) // S.ELEM_BYTES[dtype])
+        self.kind, self.dtype, self.n_max, self.rotate = kind, dtype, n_max, rotate
         td = _torch_dtype(dtype)
         cat = dict(S.salt_catalogue())
         self.route = -1
@@ -116,36 +120,57 @@ class Workload:
             self.res = torch.empty(1, dtype=torch.float64 if dtype == S.F64 else torch.float32, device="cuda")
             self.arrays = 2 if kind == "dot" else 1
 
+    def sets(self, n: int) -> int:
+        """Disjoint slices of the buffers that launches at size n cycle
+        through. Without rotation (the default) every launch reuses the same
+        buffers, so working sets below the 256 MiB last-level cache are timed
+        cache-resident, as in iterative use of the same vectors. With
+        rotation: enough slices for about 1 GiB (at most 64), so a working
+        set between 4 MiB and 1 GiB streams from HBM."""
+        ws = self.arrays * S.ELEM_BYTES[self.dtype] * n
+        if not self.rotate or ws >= (1 << 30) or ws < (4 << 20):
+            return 1
+        return int(min(64, self.n_max // n, -(-(1 << 30) // ws)))
+
     def fn(self, n: int):
+        sets, state = self.sets(n), {"k": 0}
+
+        def sl(t):
+            k = state["k"] % sets
+            return t[k * n:(k + 1) * n]
+
+        def step(call):
+            def run(cfg):
+                call(cfg)
+                state["k"] += 1
+            return run
+
         if self.kind == "dotx":
-            ops = [o[:n] for o in self.ops]
-            return lambda cfg: S.salt_dot_expr(EXPR_P, EXPR_Q, ops, [], n=n, result=self.res, ws=self.ws,
-                                               config=cfg)
+            return step(lambda cfg: S.salt_dot_expr(EXPR_P, EXPR_Q, [sl(o) for o in self.ops], [], n=n,
+                                                    result=self.res, ws=self.ws, config=cfg))
         if self.kind == "nrm2x":
-            ops = [o[:n] for o in self.ops]
-            return lambda cfg: S.salt_nrm2_expr(EXPR_P, ops, [], n=n, result=self.res, ws=self.ws, config=cfg)
+            return step(lambda cfg: S.salt_nrm2_expr(EXPR_P, [sl(o) for o in self.ops], [], n=n, result=self.res,
+                                                     ws=self.ws, config=cfg))
         if self.kind in ("eval", "interp"):
-            ops = [o[:n] for o in self.ops]
-            out = self.out[:n]
-            return lambda cfg: S.salt_eval(self.prog, ops, self.sc, out, config=cfg)
+            return step(lambda cfg: S.salt_eval(self.prog, [sl(o) for o in self.ops], self.sc, sl(self.out),
+                                                config=cfg))
         if self.kind == "dot":
-            x, y = self.x[:n], self.y[:n]
-            return lambda cfg: S.salt_dot(x, y, result=self.res, ws=self.ws, config=cfg)
-        x = self.x[:n]
-        return lambda cfg: S.salt_nrm2(x, result=self.res, ws=self.ws, config=cfg)
+            return step(lambda cfg: S.salt_dot(sl(self.x), sl(self.y), result=self.res, ws=self.ws, config=cfg))
+        return step(lambda cfg: S.salt_nrm2(sl(self.x), result=self.res, ws=self.ws, config=cfg))
 
 
-def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbose: bool = False):
+def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbose: bool = False,
+         rotate: bool = False):
     """Rows (kind, route, dtype, log2n, unroll, nt, blocks, best_ms, GBps)."""
     import torch
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    w = Workload(kind, tree, dtype, 1 << max(log2ns))
+    w = Workload(kind, tree, dtype, 1 << max(log2ns), rotate=rotate)
     rows = []
     for l in log2ns:
         n = 1 << l
         fn = w.fn(n)
-        reps_l = reps if l >= 20 else reps * 3
+        reps_l = max(reps if l >= 20 else reps * 3, w.sets(n))
         best = None
         for cfg in candidates(kind, n, dtype, cus):
             t = time_config(fn, cfg, reps_l)
@@ -252,6 +277,9 @@ def main(argv=None) -> int:
     ap.add_argument("--step", type=int, default=2, help="tune every step-th log2 size")
     ap.add_argument("--kinds", default="eval,dot,nrm2,interp,dotx,nrm2x,batch")
     ap.add_argument("--json", default=None, help="also write all rows as JSON here")
+    ap.add_argument("--rotate", action="store_true",
+                    help="time working sets of 4 MiB .. 1 GiB streaming from HBM (buffer slices cycled) "
+                         "instead of cache-resident")
     args = ap.parse_args(argv)
     lo, hi = (int(v) for v in args.log2n.split("-"))
     sizes = list(range(lo, hi + 1, args.step))
@@ -264,13 +292,13 @@ def main(argv=None) -> int:
         d = DT_NAMES[dname]
         for kind in ("dot", "nrm2"):
             if kind in kinds:
-                rows += tune(kind, None, d, sizes, args.reps, verbose=True)
+                rows += tune(kind, None, d, sizes, args.reps, verbose=True, rotate=args.rotate)
         if "eval" in kinds:
             for tree in args.trees.split(","):
-                rows += tune("eval", tree, d, sizes, args.reps, verbose=True)
+                rows += tune("eval", tree, d, sizes, args.reps, verbose=True, rotate=args.rotate)
         for kind in ("interp", "dotx", "nrm2x"):
             if kind in kinds:
-                rows += tune(kind, None, d, sizes, args.reps, verbose=True)
+                rows += tune(kind, None, d, sizes, args.reps, verbose=True, rotate=args.rotate)
     if "batch" in kinds:
         from . import workloads
 
