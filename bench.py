@@ -30,9 +30,11 @@ step):
                against 4096 separate launches and one binary64 kernel;
     served:    (only when named) Poisson request streams at fractions of the
                measured saturation rate, p50 / p99 latency and throughput.
-               It is not in the default run: one run of it after the other
-               sections in the same process ended in a GPU memory fault whose
-               cause has not been found.
+               It is left out of the default run so that the headline line
+               never depends on it: one run of it after the other sections
+               ended in a GPU memory fault, since traced to the serving loop
+               not waiting for the caller's queued work on the arenas it was
+               handed (fixed: the loop now waits for the device first).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
                     [--sections main,sweep,fusion,precision,blas1,batched[,served]]
