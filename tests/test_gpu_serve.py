@@ -91,3 +91,32 @@ def test_bad_config_is_rejected(pool):
     assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # 9 streams
     cfg = V.ServerConfig(arena.data_ptr(), 1 << 20, table.data_ptr(), 1 << 10, 16, 2, 8, 1, 1)
     assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # table too small
+
+
+def test_waits_for_callers_queued_work(pool):
+    """Regression test of an ordering gap: the loop's streams do not wait for
+    the caller's stream, so the arenas it is handed may still have queued
+    writers there (torch's caching allocator hands a freed block to the next
+    allocation on the same stream at once). Here a chain of element-wise
+    kernels is queued on a block, the block is freed, and the descriptor
+    arena and the output arena are allocated right after (the same sizes, so
+    they come from the freed blocks). The loop waits for the device before
+    its first copy, so the results are still those of each request alone."""
+    import torch
+
+    tb, ab = 16 << 20, 256 << 20
+    t = torch.empty(tb // 8, dtype=torch.float64, device="cuda")
+    a = torch.empty(ab // 8, dtype=torch.float64, device="cuda")
+    t.fill_(1.0)
+    a.fill_(1.0)
+    for _ in range(40):                 # queued work writing both blocks
+        t.mul_(1.5).add_(0.25)
+        a.mul_(1.5).add_(0.25)
+    del t, a
+    arena, table = V.default_buffers(arena_bytes=ab, table_bytes=tb)
+    trace, meta = V.make_trace(pool, 60, seed=5005, rate=None, lo=8, hi=16)
+    res = V.serve(trace, arena, table, n_streams=2, max_batch=16, keep_outputs=True)
+    torch.cuda.synchronize()
+    assert all(r.status == 0 for r in res)
+    for i, (r, m) in enumerate(zip(res, meta)):
+        assert torch.equal(served_bytes(arena, r, m), alone_bytes(pool, m)), (i, m[:3])
