@@ -101,34 +101,77 @@ def event_ms(fn, reps: int, warm: int = 2) -> float:
 # CPU baseline: the oracle on a bounded sample of the step
 # ---------------------------------------------------------------------------
 
-def cpu_baseline(log2n_sample: int, reps: int = 12):
+def host_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (the share of the host given to one
+    GPU)."""
+    try:
+        t = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        t = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        t = min(t, int(env))
+    return max(1, t)
+
+
+def cpu_baseline(log2n_sample: int, reps: int = 5):
+    """The oracle timed on the host: one step of the hot path (the 5-operand
+    tree, axpy, and the plain binary64 dot and nrm2 loops) on a bounded sample
+    of the GPU step's elements, with one thread and with every thread this
+    process may use (OpenMP shares of the element range, inputs first touched
+    by the same split). Dot2, the reference-value reduction, is timed apart."""
     import numpy as np
 
     import oracle
     from paper_1109_1264_amd import workloads
 
     n = 1 << log2n_sample
-    a, b, c, e, f = workloads.uniform(n, "f64", workloads.sweep_seed(n), 5)
+    a0, b0, c0, e0, f0 = workloads.uniform(n, "f64", workloads.sweep_seed(n), 5)
     alpha = workloads.alpha(workloads.sweep_seed(n))
     tree5 = [1, (1 << 8) | 1, 5, (2 << 8) | 1, (3 << 8) | 1, 5, 3, (4 << 8) | 1, 4]
-    times = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        d = oracle.eval_program(tree5, [a, b, c, e, f], [], "f64")
-        d = oracle.axpy(alpha, a, d, "f64")
-        oracle.dot2(a, b)
-        oracle.nrm2(c)
-        times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    return {"value": round(96.0 * n / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "one step of the same hot path (tree eval, axpy, Dot2 dot, Dot2 nrm2) on n=2^%d "
-                      "binary64 elements (of the 2^28 in the GPU step), median of %d runs, "
-                      "single-threaded plain C" % (log2n_sample, reps),
-            "seconds_per_step": round(t, 4), "host": host_cpu()}
+    threads = host_threads()
+
+    def run(T):
+        ops = [oracle.first_touch_copy(v, T) for v in (a0, b0, c0, e0, f0)]
+        a, b, c, e, f = ops
+        oracle.set_threads(T)
+        times, used = [], 1
+        try:
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                d = oracle.eval_program(tree5, ops, [], "f64")
+                d = oracle.axpy(alpha, a, d, "f64")
+                _, used = oracle.naive_dot_par(a, b, T)
+                math.sqrt(oracle.naive_dot_par(c, c, T)[0])
+                times.append(time.perf_counter() - t0)
+        finally:
+            oracle.set_threads(1)
+        return float(np.median(times)), used
+
+    t1, _ = run(1)
+    tn, used = run(threads) if threads > 1 else (t1, 1)
+    t0 = time.perf_counter()
+    oracle.dot2(a0, b0)
+    oracle.nrm2(c0)
+    t_dot2 = time.perf_counter() - t0
+    gbps = lambda t: round(96.0 * n / t / 1e9, 3)
+    return {"value": gbps(tn), "unit": "GB/s", "cores": used, "kind": "oracle",
+            "sample": "one step of the same hot path (d = a*b + c*e - f, y = alpha*x + y, plain binary64 "
+                      "dot and nrm2 loops) on n=2^%d binary64 elements (of the 2^28 in the GPU step), "
+                      "median of %d runs, %d OpenMP threads (static shares, inputs first-touched by the "
+                      "same split)" % (log2n_sample, reps, used),
+            "seconds_per_step": round(tn, 4),
+            "one_thread": {"value": gbps(t1), "seconds_per_step": round(t1, 4)},
+            "dot2_reference_seconds": {"dot_and_nrm2": round(t_dot2, 4), "threads": 1,
+                                       "what": "Dot2 (compensated) dot(a, b) and nrm2(c), the reference "
+                                               "values of the parity checks, timed apart"},
+            "host": host_cpu()}
 
 
 def host_cpu() -> dict:
-    """The host's CPU model and logical CPU count (the baseline's machine)."""
+    """The host's CPU model, sockets and logical CPU count (the baseline's
+    machine)."""
     model = None
     try:
         with open("/proc/cpuinfo") as fh:
@@ -138,7 +181,19 @@ def host_cpu() -> dict:
                     break
     except OSError:
         pass
-    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
+    lscpu = {}
+    try:
+        import subprocess
+
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                lscpu[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "threads_allowed": host_threads(),
+            "lscpu": lscpu}
 
 
 # ---------------------------------------------------------------------------

@@ -15,7 +15,11 @@ The arithmetic lives in ``salt_oracle.c`` (plain C, built with gcc and
 - :func:`axpy` -- ``y <- alpha*x + y`` (Sec. 5, xAXPY).
 - :func:`dot2`, :func:`nrm2` -- the root reductions (Sec. 2 "dot product or
   norm", Sec. 4.2 reduction step), as Dot2 values (Ogita-Rump-Oishi 2005).
-- :func:`naive_dot` -- plain sequential loops (timing baseline, FP32 mode).
+- :func:`naive_dot` -- plain sequential loops (timing baseline, FP32 mode);
+  :func:`naive_dot_par` -- the binary64 loop on several host threads (the
+  all-cores timing baseline; per-thread partials added in thread order).
+- :func:`set_threads` -- host threads for the element-wise loops (results do
+  not depend on it: each element is computed alone).
 
 16-bit storage arrays are ``numpy.uint16`` bit patterns; ``dtype`` names are
 ``"f64"``, ``"f32"``, ``"bf16"`` and ``"f16"``.
@@ -36,7 +40,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 # keeps its own copy: it shares no header with the GPU library.
 LOAD, SCALAR, ADD, SUB, MUL = 1, 2, 3, 4, 5
 
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
           "-fno-fast-math", "-fexcess-precision=standard"]
 
 
@@ -82,6 +86,14 @@ def load(path: str) -> ctypes.CDLL:
     L.oracle_naive_dot_f64.restype = D
     L.oracle_naive_dot_f32.argtypes = [I64, P, P]
     L.oracle_naive_dot_f32.restype = ctypes.c_float
+    L.oracle_naive_dot_f64_par.argtypes = [I64, P, P, I, P]
+    L.oracle_naive_dot_f64_par.restype = D
+    L.oracle_parallel_copy.argtypes = [P, P, I64, I]
+    L.oracle_parallel_copy.restype = None
+    L.oracle_set_threads.argtypes = [I]
+    L.oracle_set_threads.restype = I
+    L.oracle_get_threads.argtypes = []
+    L.oracle_get_threads.restype = I
     L.oracle_reduce_canonical.argtypes = [I, I, I64, P, P, P]
     L.oracle_reduce_canonical.restype = I
     L.oracle_copy.argtypes = [I64, P, I64, P, I64, I]
@@ -216,6 +228,38 @@ def naive_dot(x: np.ndarray, y: np.ndarray, dtype: str = "f64") -> float:
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     return float(L.oracle_naive_dot_f64(len(x), _ptr(x), _ptr(y)))
+
+
+def naive_dot_par(x: np.ndarray, y: np.ndarray, threads: int) -> tuple[float, int]:
+    """The binary64 loop split over ``threads`` host threads: thread t sums
+    elements [t*n/T, (t+1)*n/T) in order, the partials are added in thread
+    order. Returns the sum and the number of threads that ran."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    if len(x) != len(y):
+        raise ValueError("length mismatch")
+    used = ctypes.c_int(0)
+    r = lib().oracle_naive_dot_f64_par(len(x), _ptr(x), _ptr(y), int(threads), ctypes.byref(used))
+    return float(r), used.value
+
+
+def set_threads(threads: int) -> None:
+    """Host threads for the element-wise loops (eval, axpy)."""
+    if lib().oracle_set_threads(int(threads)) != 0:
+        raise ValueError("threads must be >= 1")
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
+
+
+def first_touch_copy(a: np.ndarray, threads: int) -> np.ndarray:
+    """A copy of ``a`` in fresh memory written by ``threads`` threads, each
+    one contiguous share (so its pages sit near the thread that uses them)."""
+    a = np.ascontiguousarray(a)
+    out = np.empty_like(a)
+    lib().oracle_parallel_copy(_ptr(out), _ptr(a), a.nbytes, int(threads))
+    return out
 
 
 _KIND = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}

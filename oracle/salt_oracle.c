@@ -6,8 +6,9 @@
  * benchmark's CPU-baseline leg are the only code allowed to load this
  * library. The GPU product path never calls it, and the two share no code.
  *
- * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -fno-fast-math
- *        (contraction off: every add, sub and mul is one IEEE operation).
+ * Build: gcc -O2 -std=c11 -fPIC -shared -fopenmp -ffp-contract=off
+ *        -fno-fast-math (contraction off: every add, sub and mul is one IEEE
+ *        operation).
  *
  * What is computed, and the passage each function follows:
  *  - oracle_eval_*: the expression tree is evaluated lazily at assignment,
@@ -28,6 +29,13 @@
  *    sqrt(sum x_i^2), from Dot2(x, x).
  *  - oracle_naive_dot_*: plain sequential loops, kept as a CPU timing baseline
  *    and as the same-precision FP32 mode (not a reference value at large n).
+ *    oracle_naive_dot_f64_par is the all-cores form of the binary64 loop:
+ *    each of T threads sums one contiguous share of the elements in order,
+ *    and the T partial sums are added in thread order (the OpenMP layer of
+ *    Sec. 6 applied to the timing baseline).
+ *  - oracle_set_threads: the element-wise loops (eval, axpy) run on that many
+ *    host threads, OpenMP static shares of the element range. Each element is
+ *    computed alone, so the results do not depend on the thread count.
  *  - oracle_reduce_canonical: a second, bit-exact reduction oracle. The
  *    paper's reduction keeps per-slot partial sums and ends with a
  *    reduction step (Sec. 4.2) without fixing an order; the library fixes
@@ -53,6 +61,7 @@
  * the compute type), ADD=3, SUB=4, MUL=5 (pop r, pop l, push l op r).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -65,6 +74,17 @@
 #define OR_MAX_STACK 64
 
 /* Return codes: 0 ok, 1 bad program / argument. */
+
+/* Host threads for the element-wise loops (1 unless set). */
+static int g_threads = 1;
+
+int oracle_set_threads(int t) {
+    if (t < 1) return 1;
+    g_threads = t;
+    return 0;
+}
+
+int oracle_get_threads(void) { return g_threads; }
 
 /* ---- program check (the oracle's own, minimal) ---------------------------- */
 static int check_program(const uint32_t *prog, int len, int n_ops, int n_sc) {
@@ -166,8 +186,9 @@ void oracle_narrow_h16(int kind, const float *f, uint16_t *out, int64_t n) {
 int oracle_eval_f64(const uint32_t *prog, int len, const double *const *ops, int n_ops,
                     const double *scalars, int n_sc, double *out, int64_t n) {
     if (check_program(prog, len, n_ops, n_sc) || n < 0) return 1;
-    double st[OR_MAX_STACK];
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < n; ++i) {
+        double st[OR_MAX_STACK];
         int sp = 0;
         for (int t = 0; t < len; ++t) {
             uint32_t op = prog[t] & 0xffu, arg = prog[t] >> 8;
@@ -184,8 +205,9 @@ int oracle_eval_f64(const uint32_t *prog, int len, const double *const *ops, int
 int oracle_eval_f32(const uint32_t *prog, int len, const float *const *ops, int n_ops,
                     const double *scalars, int n_sc, float *out, int64_t n) {
     if (check_program(prog, len, n_ops, n_sc) || n < 0) return 1;
-    float st[OR_MAX_STACK];
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < n; ++i) {
+        float st[OR_MAX_STACK];
         int sp = 0;
         for (int t = 0; t < len; ++t) {
             uint32_t op = prog[t] & 0xffu, arg = prog[t] >> 8;
@@ -204,8 +226,9 @@ int oracle_eval_f32(const uint32_t *prog, int len, const float *const *ops, int 
 int oracle_eval_h16(int kind, const uint32_t *prog, int len, const uint16_t *const *ops,
                     int n_ops, const double *scalars, int n_sc, uint16_t *out, int64_t n) {
     if (check_program(prog, len, n_ops, n_sc) || n < 0 || (kind != 0 && kind != 1)) return 1;
-    float st[OR_MAX_STACK];
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < n; ++i) {
+        float st[OR_MAX_STACK];
         int sp = 0;
         for (int t = 0; t < len; ++t) {
             uint32_t op = prog[t] & 0xffu, arg = prog[t] >> 8;
@@ -227,6 +250,7 @@ int oracle_eval_h16(int kind, const uint32_t *prog, int len, const uint16_t *con
 
 int oracle_axpy_f64(int64_t n, double alpha, const double *x, double *y) {
     if (n < 0) return 1;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < n; ++i) y[i] = alpha * x[i] + y[i];
     return 0;
 }
@@ -234,6 +258,7 @@ int oracle_axpy_f64(int64_t n, double alpha, const double *x, double *y) {
 int oracle_axpy_f32(int64_t n, double alpha, const float *x, float *y) {
     if (n < 0) return 1;
     float a = (float)alpha;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < n; ++i) y[i] = a * x[i] + y[i];
     return 0;
 }
@@ -290,6 +315,43 @@ float oracle_naive_dot_f32(int64_t n, const float *x, const float *y) {
     float s = 0.0f;
     for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];
     return s;
+}
+
+/* Thread t of T owns elements [t*n/T, (t+1)*n/T) and sums them in order;
+ * the partials are then added in thread order. *used gets the number of
+ * threads that ran. The value depends on T (and equals the sequential loop's
+ * for T = 1). */
+double oracle_naive_dot_f64_par(int64_t n, const double *x, const double *y, int threads, int *used) {
+    if (threads < 1) threads = 1;
+    double part[256];
+    if (threads > 256) threads = 256;
+    int ran = 1;
+#pragma omp parallel num_threads(threads) if (threads > 1)
+    {
+        const int T = omp_get_num_threads(), t = omp_get_thread_num();
+        if (t == 0) ran = T;
+        const int64_t lo = (int64_t)((__int128)n * t / T), hi = (int64_t)((__int128)n * (t + 1) / T);
+        double s = 0.0;
+        for (int64_t i = lo; i < hi; ++i) s = s + x[i] * y[i];
+        part[t] = s;
+    }
+    double s = 0.0;
+    for (int t = 0; t < ran; ++t) s = s + part[t];
+    if (used) *used = ran;
+    return s;
+}
+
+/* Copy nbytes with each of `threads` threads writing one contiguous share, so
+ * that a fresh destination is first touched by the same split the parallel
+ * loops above use. */
+void oracle_parallel_copy(void *dst, const void *src, int64_t nbytes, int threads) {
+    if (threads < 1) threads = 1;
+#pragma omp parallel num_threads(threads) if (threads > 1)
+    {
+        const int T = omp_get_num_threads(), t = omp_get_thread_num();
+        const int64_t lo = (int64_t)((__int128)nbytes * t / T), hi = (int64_t)((__int128)nbytes * (t + 1) / T);
+        memcpy((char *)dst + lo, (const char *)src + lo, (size_t)(hi - lo));
+    }
 }
 
 /* ---- the canonical summation order (second reduction oracle) -------------- */

@@ -24,8 +24,12 @@ def test_cpu_baseline_record():
     import bench
 
     rec = bench.cpu_baseline(12, reps=1)
-    assert rec["kind"] == "oracle" and rec["unit"] == "GB/s" and rec["cores"] == 1
+    assert rec["kind"] == "oracle" and rec["unit"] == "GB/s"
+    # all the threads the process may use, and a one-thread figure beside them
+    assert rec["cores"] == bench.host_threads() >= 1
     assert rec["value"] > 0 and rec["seconds_per_step"] > 0
+    assert rec["one_thread"]["value"] > 0
+    assert rec["dot2_reference_seconds"]["dot_and_nrm2"] > 0
     assert "n=2^12" in rec["sample"]
     assert rec["host"]["logical_cpus"] == os.cpu_count()
     json.dumps(rec)  # one JSON line

@@ -47,6 +47,24 @@ MUTANTS = {
     # naive loop accumulating in the wrong precision
     "naive_f32_in_f64": ("float s = 0.0f;\n    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];",
                          "double s = 0.0;\n    for (int64_t i = 0; i < n; ++i) s = s + (double)x[i] * y[i];"),
+    # the binary64 loop accumulating in binary32
+    "naive_f64_in_f32": ("double s = 0.0;\n    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];\n    return s;",
+                         "float s = 0.0f;\n    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];\n    return s;"),
+    # the binary64 loop dropping the last element
+    "naive_f64_drop_last": ("double s = 0.0;\n    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];\n    return s;",
+                            "double s = 0.0;\n    for (int64_t i = 0; i + 1 < n; ++i) s = s + x[i] * y[i];\n    return s;"),
+    # the binary64 loop with a fused multiply-add
+    "naive_f64_fma": ("double s = 0.0;\n    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];\n    return s;",
+                      "double s = 0.0;\n    for (int64_t i = 0; i < n; ++i) s = fma(x[i], y[i], s);\n    return s;"),
+    # the binary64 loop returning the Dot2 value
+    "naive_f64_is_dot2": ("double s = 0.0;\n    for (int64_t i = 0; i < n; ++i) s = s + x[i] * y[i];\n    return s;",
+                          "double s = 0.0;\n    oracle_dot2(n, x, y, &s, 0);\n    return s;"),
+    # the all-cores loop adding its partials in reverse thread order
+    "naive_par_reverse": ("for (int t = 0; t < ran; ++t) s = s + part[t];",
+                          "for (int t = ran - 1; t >= 0; --t) s = s + part[t];"),
+    # the all-cores loop giving the first threads the remainder
+    "naive_par_split": ("hi = (int64_t)((__int128)n * (t + 1) / T);",
+                        "hi = t + 1 == T ? n : (int64_t)((__int128)n * (t + 1) / T + (n % T ? 1 : 0));"),
     # negative increments walking forward instead of from the far end
     "blas_negative_forward": ("return inc >= 0 ? i * inc : (n - 1 - i) * (-inc);",
                               "return inc >= 0 ? i * inc : i * (-inc);"),

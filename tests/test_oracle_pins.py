@@ -338,6 +338,71 @@ def check_naive_f32(o):
     assert o.naive_dot(x, y, "f32") == float(s)
 
 
+def check_naive_f64(o):
+    """The binary64 loop adds the products one by one, in element order, each
+    product rounded before its addition. Every value below is worked by hand
+    from that definition."""
+    big = 2.0 ** 53
+    one = np.ones(3)
+    # order: 2^53 + 1 rounds (tie) back to 2^53, twice; a pairwise, reversed,
+    # compensated or Dot2 sum gives 2^53 + 2
+    assert o.naive_dot(np.array([big, 1.0, 1.0]), one) == big
+    # precision: 1 + 2^-30 is exact in binary64 and rounds to 1 in binary32
+    assert o.naive_dot(np.array([1.0, 2.0 ** -30]), np.ones(2)) == 1.0 + 2.0 ** -30
+    # the last element counts
+    assert o.naive_dot(np.array([0.0, 0.0, 5.0]), one) == 5.0
+    # no contraction: (1 + 2^-27)(1 - 2^-27) = 1 - 2^-54 rounds (tie, to even)
+    # to 1, so -1 + 1 = 0; a fused multiply-add would keep -2^-54
+    assert o.naive_dot(np.array([1.0, 1.0 + 2.0 ** -27]), np.array([-1.0, 1.0 - 2.0 ** -27])) == 0.0
+    # integer data: exact in any order (closed form n(n-1)(2n-1)/3)
+    n = 1000
+    i = np.arange(n, dtype=np.float64)
+    assert o.naive_dot(i, 2 * i) == n * (n - 1) * (2 * n - 1) / 3
+    assert o.naive_dot(np.zeros(0), np.zeros(0)) == 0.0
+
+
+def check_naive_par(o):
+    """All-cores form: thread t of T sums elements [t*n/T, (t+1)*n/T) in order
+    and the partials are added in thread order; values worked by hand."""
+    big = 2.0 ** 53
+    # T = 1 is the sequential loop
+    x, y = workloads.uniform(5000, "f64", 12, 2)
+    assert o.naive_dot_par(x, y, 1) == (o.naive_dot(x, y), 1)
+    # n = 4, T = 2: shares [2^53, 1] -> 2^53 and [1, 1] -> 2; total 2^53 + 2
+    assert o.naive_dot_par(np.array([big, 1.0, 1.0, 1.0]), np.ones(4), 2) == (big + 2, 2)
+    # n = 5, T = 2: shares [0, 2) and [2, 5): 2^53 and 3; 2^53 + 3 ties to
+    # 2^53 + 4 (a [0, 3) / [3, 5) split would give 2^53 + 2)
+    assert o.naive_dot_par(np.array([big, 1.0, 1.0, 1.0, 1.0]), np.ones(5), 2)[0] == big + 4
+    # n = 3, T = 3: partials 2^53, 1, 1 added in thread order give 2^53
+    # (in reverse order 2^53 + 2)
+    assert o.naive_dot_par(np.array([big, 1.0, 1.0]), np.ones(3), 3)[0] == big
+    # integer data: exact for any split
+    i = np.arange(3001, dtype=np.float64)
+    assert o.naive_dot_par(i, 2 * i, 7) == (3001 * 3000 * 6001 / 3, 7)
+
+
+def check_eval_threads(o):
+    """The element-wise loops on several threads give the one-thread bits
+    (each element is computed alone)."""
+    prog = [tok(LOAD, 0), tok(LOAD, 1), tok(MUL), tok(LOAD, 2), tok(LOAD, 3), tok(MUL), tok(ADD),
+            tok(LOAD, 4), tok(SUB)]
+    for dt in ("f64", "f32"):
+        ops = workloads.uniform(100003, dt, 21, 5)
+        one = o.eval_program(prog, ops, [], dt)
+        ax1 = o.axpy(1.375, ops[0], ops[1], dt)
+        o.set_threads(5)
+        try:
+            many = o.eval_program(prog, ops, [], dt)
+            ax5 = o.axpy(1.375, ops[0], ops[1], dt)
+        finally:
+            o.set_threads(1)
+        assert np.array_equal(one.view(np.uint8), many.view(np.uint8))
+        assert np.array_equal(ax1.view(np.uint8), ax5.view(np.uint8))
+        # and the values are the trees' (numpy evaluates the same operations)
+        a, b, c, e, f = ops
+        assert np.array_equal(many, (a * b + c * e) - f)
+
+
 # --------------------------------------------------------------------------
 # the tests
 # --------------------------------------------------------------------------
@@ -555,6 +620,9 @@ CHECKS = {
     "dot_fsum": check_dot_fsum,
     "nrm2": check_nrm2,
     "naive_f32": check_naive_f32,
+    "naive_f64": check_naive_f64,
+    "naive_par": check_naive_par,
+    "eval_threads": check_eval_threads,
     "blas_strides": check_blas_strides,
     "scal_axpy_strided": check_scal_axpy_strided,
     "asum": check_asum,
