@@ -28,16 +28,15 @@ step):
     batched:   4096 lognormal-length instances of alpha*a + (b - c) plus
                dot(a, b) in one persistent launch replayed from a HIP graph,
                against 4096 separate launches and one binary64 kernel;
-    served:    (only when named) Poisson request streams at fractions of the
-               measured saturation rate, p50 / p99 latency and throughput.
-               It is left out of the default run so that the headline line
-               never depends on it: one run of it after the other sections
-               ended in a GPU memory fault, since traced to the serving loop
-               not waiting for the caller's queued work on the arenas it was
-               handed (fixed: the loop now waits for the device first).
+    served:    Poisson request streams over five trees (binary32 / bfloat16 /
+               binary64 mix, lengths 2^8..2^24, 64 GB resident pool) at
+               fractions of the measured saturation rate: p50 / p99 latency
+               and throughput; then one more stream served with kept outputs,
+               each request's output checked bit for bit against the oracle
+               on sampled elements (served_parity_ok).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
-                    [--sections main,sweep,fusion,precision,blas1,batched[,served]]
+                    [--sections main,sweep,fusion,precision,blas1,batched,served]
 """
 from __future__ import annotations
 
@@ -163,7 +162,7 @@ def cpu_baseline(log2n_sample: int, reps: int = 5):
                       "same split)" % (log2n_sample, reps, used),
             "seconds_per_step": round(tn, 4),
             "one_thread": {"value": gbps(t1), "seconds_per_step": round(t1, 4)},
-            "dot2_reference_seconds": {"dot_and_nrm2": round(t_dot2, 4), "threads": 1,
+            "dot2_reference_seconds": {"dot_and_nrm2": float("%.4g" % t_dot2), "threads": 1,
                                        "what": "Dot2 (compensated) dot(a, b) and nrm2(c), the reference "
                                                "values of the parity checks, timed apart"},
             "host": host_cpu()}
@@ -524,7 +523,26 @@ def fig1_small() -> dict:
 # precision layer
 # ---------------------------------------------------------------------------
 
+def rotated_graph_ms(fns, reps: int) -> float:
+    """Per-launch device time of a captured graph of `reps` launches that
+    cycles through `fns` (one per buffer set): each launch reads a set that
+    the launches in between have pushed out of the last-level cache."""
+    state = {"k": 0}
+
+    def step():
+        fns[state["k"] % len(fns)]()
+        state["k"] += 1
+    return graph_ms(step, reps)
+
+
 def section_precision(args):
+    """dot and nrm2 at n = 2^26 with the operands stored in binary64, binary32
+    and bfloat16 (ill-conditioned values), each from HBM: the timed launches
+    cycle through copies of the operands (at least 4 sets and 2 GiB, so a
+    set was evicted from the 256 MiB last-level cache before it is read
+    again). Pass 1 alone (salt_reduce_partials) is timed beside the whole
+    call, so the pass-2 launch is reported apart; the same call on one set
+    (cache-resident where the set fits the cache) is reported as well."""
     import numpy as np
     import torch
 
@@ -538,29 +556,57 @@ def section_precision(args):
     exact_dot, abs_dot = oracle.dot2(x64, y64)
     exact_nrm = oracle.nrm2(x64)
     rows = {}
-    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
     for name in ("f64", "f32", "bf16"):
         code = {"f64": salt.F64, "f32": salt.F32, "bf16": salt.BF16}[name]
+        es = {"f64": 8, "f32": 4, "bf16": 2}[name]
         xs, ys = workloads.store(x64, name), workloads.store(y64, name)
         if name == "bf16":
-            dx = torch.from_numpy(xs.view(np.int16)).view(torch.bfloat16).cuda()
-            dy = torch.from_numpy(ys.view(np.int16)).view(torch.bfloat16).cuda()
+            hx = torch.from_numpy(xs.view(np.int16)).view(torch.bfloat16)
+            hy = torch.from_numpy(ys.view(np.int16)).view(torch.bfloat16)
         else:
-            dx, dy = torch.from_numpy(xs).cuda(), torch.from_numpy(ys).cuda()
+            hx, hy = torch.from_numpy(xs), torch.from_numpy(ys)
+        set_bytes = 2 * es * n
+        sets = max(4, -(-(2 << 30) // set_bytes))
+        dx = [hx.cuda() for _ in range(sets)]
+        dy = [hy.cuda() for _ in range(sets)]
         ws = salt.workspace(n, code)
-        r1 = torch.empty(1, dtype=torch.float64 if name == "f64" else torch.float32, device="cuda")
-        r2 = torch.empty_like(r1)
-        t_dot = event_ms(lambda: salt.salt_dot(dx, dy, result=r1, ws=ws), 20)
-        t_nrm = event_ms(lambda: salt.salt_nrm2(dx, result=r2, ws=ws), 20)
+        tiles = salt.salt_reduce_workspace_bytes(n, code) // 8
+        part = torch.empty(tiles, dtype=torch.float64, device="cuda")
+        rdt = torch.float64 if name == "f64" else torch.float32
+        r_dot = torch.empty(sets, dtype=rdt, device="cuda")
+        r_nrm = torch.empty(sets, dtype=rdt, device="cuda")
+        dots = [lambda k=k: salt.salt_dot(dx[k], dy[k], result=r_dot[k:k + 1], ws=ws) for k in range(sets)]
+        nrms = [lambda k=k: salt.salt_nrm2(dx[k], result=r_nrm[k:k + 1], ws=ws) for k in range(sets)]
+        p1_dot = [lambda k=k: salt.salt_reduce_partials(salt.MODE_DOT, dx[k], dy[k], partials=part)
+                  for k in range(sets)]
+        p1_nrm = [lambda k=k: salt.salt_reduce_partials(salt.MODE_NRM2, dx[k], partials=part) for k in range(sets)]
+        reps = 8 * sets
+        t_dot = rotated_graph_ms(dots, reps)
+        t_nrm = rotated_graph_ms(nrms, reps)
+        t_dot1 = rotated_graph_ms(p1_dot, reps)
+        t_nrm1 = rotated_graph_ms(p1_nrm, reps)
+        t_dot_res = graph_ms(dots[0], reps)
+        t_nrm_res = graph_ms(nrms[0], reps)
         torch.cuda.synchronize()
-        got_dot, got_nrm = float(r1.item()), float(r2.item())
+        # every set holds the same values, so every set's result has the same bits
+        same = bool(torch.equal(r_dot, r_dot[:1].expand(sets)) and torch.equal(r_nrm, r_nrm[:1].expand(sets)))
+        got_dot, got_nrm = float(r_dot[0].item()), float(r_nrm[0].item())
         wx, wy = oracle.widen(xs, name), oracle.widen(ys, name)
         q_dot, q_abs = oracle.dot2(wx, wy)
         q_nrm = oracle.nrm2(wx)
-        es = {"f64": 8, "f32": 4, "bf16": 2}[name]
+        gb = lambda nbytes, t: round(nbytes / (t * 1e-3) / 1e9, 1)
         rows[name] = {
-            "dot_ms": round(t_dot, 4), "dot_GBps": round(2 * es * n / (t_dot * 1e-3) / 1e9, 1),
-            "nrm2_ms": round(t_nrm, 4), "nrm2_GBps": round(es * n / (t_nrm * 1e-3) / 1e9, 1),
+            "regime": "hbm: %d buffer sets (%d MiB) cycled launch by launch" % (sets, sets * set_bytes >> 20),
+            "dot_ms": round(t_dot, 4), "dot_GBps": gb(2 * es * n, t_dot),
+            "dot_pass1_ms": round(t_dot1, 4), "dot_pass1_GBps": gb(2 * es * n, t_dot1),
+            "nrm2_ms": round(t_nrm, 4), "nrm2_GBps": gb(es * n, t_nrm),
+            "nrm2_pass1_ms": round(t_nrm1, 4), "nrm2_pass1_GBps": gb(es * n, t_nrm1),
+            "pass2_ms_approx": round(0.5 * ((t_dot - t_dot1) + (t_nrm - t_nrm1)), 4),
+            "one_set_reused": {"what": "the same buffers every launch (set of %d MiB; %s)"
+                                       % (set_bytes >> 20, "fits the 256 MiB last-level cache"
+                                          if set_bytes <= (256 << 20) else "larger than the last-level cache"),
+                               "dot_ms": round(t_dot_res, 4), "dot_GBps": gb(2 * es * n, t_dot_res),
+                               "nrm2_ms": round(t_nrm_res, 4), "nrm2_GBps": gb(es * n, t_nrm_res)},
             "accumulation": "binary64 fma" if name == "f64" else
                             ("compensated binary32 (TwoProduct+TwoSum)" if name == "f32" else
                              "compensated binary32 (exact products, TwoSum)") + ", binary64 combine",
@@ -571,12 +617,14 @@ def section_precision(args):
             "dot_err_vs_stored": abs(got_dot - q_dot) / q_abs,
             "nrm2_err_vs_stored": abs(got_nrm - q_nrm) / q_nrm,
             "tol": oracle.TOL[name],
+            "same_bits_every_set": same,
         }
         rows[name]["within_tol"] = bool(rows[name]["dot_err_vs_stored"] <= oracle.TOL[name]
-                                        and rows[name]["nrm2_err_vs_stored"] <= oracle.TOL[name])
-        del dx, dy, ws
+                                        and rows[name]["nrm2_err_vs_stored"] <= oracle.TOL[name] and same)
+        del dx, dy, ws, part
         torch.cuda.empty_cache()
     return {"n": n, "inputs": "random sign, log10|x| ~ U[-4,4] (seed 3000), stored with RNE",
+            "timing": "per-launch device time from a replayed graph of back-to-back launches",
             "errors_are": "relative to sum|x_i y_i| (dot) or to the norm (nrm2)", "by_storage": rows}
 
 
@@ -731,9 +779,51 @@ def section_served(args):
     trace, meta = V.make_trace(pool, args.served_requests, seed=workloads.SEED_SERVED + 50, rate=0.5 * rate_sat,
                                fp64_only=True, mix=(("f64", 1.0),))
     out["poisson_0.5_all_f64"] = V.summarize(V.serve(trace, arena, table), meta)
+    if not args.no_parity:
+        out["parity"] = served_parity(V, pool, arena, table, 0.5 * rate_sat, args.served_parity_requests)
+        out["served_parity_ok"] = out["parity"]["ok"]
     del pool, arena, table
     torch.cuda.empty_cache()
     return out
+
+
+def served_parity(V, pool, arena, table, rate, count):
+    """A Poisson stream of the same workload served with kept outputs; every
+    request's output is compared bit for bit with the oracle's evaluation of
+    its tree on host copies of its operands, at 4096 random elements plus its
+    first and last 1024 (all elements when it is shorter)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1109_1264_amd import salt, workloads
+
+    log("bench: served parity, %d requests against the oracle" % count)
+    trace, meta = V.make_trace(pool, count, seed=workloads.SEED_SERVED + 77, rate=rate)
+    res = V.serve(trace, arena, table, keep_outputs=True)
+    torch.cuda.synchronize()
+    cat = dict(salt.salt_catalogue())
+    bits = {"f64": np.uint64, "f32": np.uint32, "bf16": np.uint16}
+    rng = np.random.Generator(np.random.PCG64(workloads.SEED_SERVED + 78))
+    bad, elems = [], 0
+    for i, (r, m) in enumerate(zip(res, meta)):
+        tree, dt, n, offs, alpha = m
+        if r.status != 0:
+            bad.append(i)
+            continue
+        idx = None if n <= 4096 + 2048 else np.unique(np.concatenate(
+            [rng.integers(0, n, 4096), np.arange(1024), np.arange(n - 1024, n)]))
+        ops, got = V.request_host_bits(pool, arena, r, m, idx)
+        want = oracle.eval_program(cat[tree], ops, [alpha], dt)
+        if not np.array_equal(got.view(bits[dt]), want.view(bits[dt])):
+            bad.append(i)
+        elems += n if idx is None else len(idx)
+    combos = sorted({"%s/%s" % (m[0], m[1]) for m in meta})
+    return {"requests": count, "elements_checked": int(elems), "tree_dtype_pairs": len(combos),
+            "max_n": int(max(m[2] for m in meta)), "mismatched_requests": bad[:20],
+            "what": "served outputs (kept) vs the oracle on host copies of each request's operands, "
+                    "bit for bit, 4096 random elements + first/last 1024 per request",
+            "ok": not bad}
 
 
 def main() -> int:
@@ -742,12 +832,13 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--sections", default="main,sweep,fusion,precision,blas1,batched")
+    ap.add_argument("--sections", default="main,sweep,fusion,precision,blas1,batched,served")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-log2n", type=int, default=26)
     ap.add_argument("--pool-gb", type=int, default=64)
     ap.add_argument("--served-requests", type=int, default=10000)
+    ap.add_argument("--served-parity-requests", type=int, default=1000)
     ap.add_argument("--kernels-only", default=None,
                     help="comma list of tree5,axpy,dot,nrm2,copy: launch only these, --steps times "
                          "each, and print nothing (for counter collection)")
@@ -782,6 +873,12 @@ def main() -> int:
         out["batched"] = section_batched(args)
     if "served" in sections:
         out["served"] = section_served(args)
+        sv = out["served"]
+        out["served_summary"] = {
+            "saturation_rps": sv["saturation"]["throughput_rps"], "saturation_GBps": sv["saturation"]["GBps"],
+            "p50_ms_at_0.9": sv["poisson"]["0.9"]["p50_ms"], "p99_ms_at_0.9": sv["poisson"]["0.9"]["p99_ms"],
+            "p50_ms_at_0.5": sv["poisson"]["0.5"]["p50_ms"], "p99_ms_at_0.5": sv["poisson"]["0.5"]["p99_ms"],
+            "served_parity_ok": sv.get("served_parity_ok")}
     if not args.no_cpu_baseline and "main" in sections:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2n)

@@ -120,6 +120,8 @@ def make_trace(pool: Pool, count: int, seed: int, rate: float | None, lo: int = 
         r.tree = ids[tree]
         r.dtype = DT[dt]
         r.n = n
+        if n > pool.elems(dt):
+            raise ValueError("request length %d exceeds the %s pool (%d elements)" % (n, dt, pool.elems(dt)))
         span = pool.elems(dt) - n
         offs = []
         for k in range(tree_loads(tree)):
@@ -129,6 +131,32 @@ def make_trace(pool: Pool, count: int, seed: int, rate: float | None, lo: int = 
         r.scalars[0] = float(rng.uniform(0.5, 2.0))
         meta.append((tree, dt, n, offs, r.scalars[0]))
     return arr, meta
+
+
+def request_host_bits(pool: Pool, arena, r, m, idx=None):
+    """Host copies of one served request: its operand values and its output
+    at element indices ``idx`` (all elements when None), as numpy arrays of
+    the storage type (16-bit types as uint16 bit patterns). The output is read
+    from the arena, so the request must have been served with kept outputs."""
+    import torch
+
+    tree, dt, n, offs, _ = m
+    src = pool.buf[dt]
+    es = src.element_size()
+    off = (r.out - arena.data_ptr()) // es
+    if (r.out - arena.data_ptr()) % es:
+        raise ValueError("output not aligned to its element size")
+    out_view = arena.view(src.dtype)[off:off + n]
+    ti = None if idx is None else torch.as_tensor(np.asarray(idx, dtype=np.int64), device=src.device)
+
+    def host(t):
+        t = t if ti is None else t.index_select(0, ti)
+        t = t.cpu()
+        if dt in ("bf16", "f16"):
+            return t.view(torch.int16).numpy().view(np.uint16).copy()
+        return t.numpy().copy()
+    ops = [host(src[o:o + n]) for o in offs]
+    return ops, host(out_view)
 
 
 def serve(trace, arena, table, max_inflight=4096, n_streams=4, max_batch=512, depth=2, keep_outputs=False):

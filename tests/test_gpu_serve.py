@@ -1,9 +1,15 @@
-"""The serving loop: every served result equals the same request run alone
-(bit-exact), admission by memory works under tight budgets, requests that
-can never fit are rejected instead of hanging, and the recorded times are
-ordered."""
+"""The serving loop: every served result equals the oracle's evaluation of
+the same request (bit-exact, on host copies of its operand slices) and the
+same request run alone; admission by memory works under tight budgets,
+requests that can never fit are rejected instead of hanging, and the
+recorded times are ordered. One test runs the serving workload's shapes:
+all five trees in binary64, binary32 and bfloat16, lengths up to 2^24, a
+multi-GB pool and a Poisson stream."""
 from __future__ import annotations
 
+import sys
+
+import numpy as np
 import pytest
 
 from paper_1109_1264_amd import salt as S
@@ -12,11 +18,37 @@ from paper_1109_1264_amd import serve as V
 pytestmark = pytest.mark.gpu
 
 ES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+BITS = {"f64": np.uint64, "f32": np.uint32, "bf16": np.uint16, "f16": np.uint16}
 
 
 @pytest.fixture(scope="module")
 def pool():
     return V.Pool(256 << 20, seed=5000)
+
+
+def sample_indices(n: int, seed: int, k: int = 1 << 16, edge: int = 4096) -> np.ndarray | None:
+    """Every element (None) for short requests; else k random indices plus
+    the first and last `edge` elements (the first and last tiles)."""
+    if n <= k + 2 * edge:
+        return None
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.unique(np.concatenate([rng.integers(0, n, k), np.arange(edge), np.arange(n - edge, n)]))
+
+
+def check_against_oracle(orc, pool, arena, res, meta, seed=0):
+    """Each served output, at every element or at sampled ones, against the
+    oracle evaluating the request's tree on host copies of its operands."""
+    cat = dict(S.salt_catalogue())
+    checked = 0
+    for i, (r, m) in enumerate(zip(res, meta)):
+        tree, dt, n, offs, alpha = m
+        idx = sample_indices(n, seed + i)
+        ops, got = V.request_host_bits(pool, arena, r, m, idx)
+        want = orc.eval_program(cat[tree], ops, [alpha], dt)
+        ok = np.array_equal(np.ascontiguousarray(got).view(BITS[dt]), want.view(BITS[dt]))
+        assert ok, ("request", i, tree, dt, n, "sampled" if idx is not None else "full")
+        checked += n if idx is None else len(idx)
+    return checked
 
 
 def alone_bytes(pool, m):
@@ -35,7 +67,7 @@ def served_bytes(arena, r, m):
     return arena.view(__import__("torch").uint8)[off:off + m[2] * ES[m[1]]]
 
 
-def test_served_equals_alone(pool):
+def test_served_equals_oracle_and_alone(pool, orc):
     import torch
 
     arena, table = V.default_buffers(arena_bytes=1 << 30, table_bytes=16 << 20)
@@ -45,6 +77,8 @@ def test_served_equals_alone(pool):
     batches = {r.batch for r in res}
     assert len(batches) > 1                       # work was split into several launches
     assert all(r.status == 0 for r in res)
+    # every element of every output against the oracle
+    assert check_against_oracle(orc, pool, arena, res, meta) == sum(m[2] for m in meta)
     for i, (r, m) in enumerate(zip(res, meta)):
         got = served_bytes(arena, r, m)
         want = alone_bytes(pool, m)
@@ -93,7 +127,7 @@ def test_bad_config_is_rejected(pool):
     assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # table too small
 
 
-def test_waits_for_callers_queued_work(pool):
+def test_waits_for_callers_queued_work(pool, orc):
     """Regression test of an ordering gap: the loop's streams do not wait for
     the caller's stream, so the arenas it is handed may still have queued
     writers there (torch's caching allocator hands a freed block to the next
@@ -118,5 +152,37 @@ def test_waits_for_callers_queued_work(pool):
     res = V.serve(trace, arena, table, n_streams=2, max_batch=16, keep_outputs=True)
     torch.cuda.synchronize()
     assert all(r.status == 0 for r in res)
+    check_against_oracle(orc, pool, arena, res, meta, seed=11)
     for i, (r, m) in enumerate(zip(res, meta)):
         assert torch.equal(served_bytes(arena, r, m), alone_bytes(pool, m)), (i, m[:3])
+
+
+def test_serving_workload_shapes_against_oracle(orc):
+    """The serving workload's shapes: the five trees in binary32, bfloat16 and
+    binary64 (the 50/30/20 mix), lengths log-uniform up to 2^24, a 6 GB
+    resident pool, Poisson arrivals while earlier batches run. Every output
+    is checked against the oracle (all elements up to 2^16 + 8192, else 2^16
+    sampled ones plus the first and last 4096) and bit for bit against the
+    same request run alone."""
+    import torch
+
+    big = V.Pool(6 << 30, seed=5000)
+    arena, table = V.default_buffers(arena_bytes=24 << 30, table_bytes=64 << 20)
+    trace, meta = V.make_trace(big, 600, seed=5010, rate=60000.0, lo=8, hi=24)
+    combos = {(m[0], m[1]) for m in meta}
+    assert combos == {(t, d) for t in V.TREES for d in ("f32", "bf16", "f64")}
+    assert max(m[2] for m in meta) > (1 << 23)
+    print("serving workload shapes: 600 requests, %d elements" % sum(m[2] for m in meta), flush=True)
+    sys.stdout.flush()
+    res = V.serve(trace, arena, table, keep_outputs=True)
+    torch.cuda.synchronize()
+    assert all(r.status == 0 for r in res)
+    assert len({r.batch for r in res}) > 10        # continuous batching, not one batch
+    checked = check_against_oracle(orc, big, arena, res, meta, seed=77)
+    assert checked > 600 * 256
+    for i, (r, m) in enumerate(zip(res, meta)):
+        assert torch.equal(served_bytes(arena, r, m), alone_bytes(big, m)), (i, m[:3])
+    s = V.summarize(res, meta)
+    assert s["requests"] == 600 and s["p99_ms"] >= s["p50_ms"] > 0
+    del big, arena, table
+    torch.cuda.empty_cache()
