@@ -35,14 +35,15 @@ def sample_indices(n: int, seed: int, k: int = 1 << 16, edge: int = 4096) -> np.
     return np.unique(np.concatenate([rng.integers(0, n, k), np.arange(edge), np.arange(n - edge, n)]))
 
 
-def check_against_oracle(orc, pool, arena, res, meta, seed=0):
-    """Each served output, at every element or at sampled ones, against the
-    oracle evaluating the request's tree on host copies of its operands."""
+def check_against_oracle(orc, pool, arena, res, meta, seed=0, full=False):
+    """Each served output, at every element (all of them when `full`) or at
+    sampled ones, against the oracle evaluating the request's tree on host
+    copies of its operands. Returns the number of elements compared."""
     cat = dict(S.salt_catalogue())
     checked = 0
     for i, (r, m) in enumerate(zip(res, meta)):
         tree, dt, n, offs, alpha = m
-        idx = sample_indices(n, seed + i)
+        idx = None if full else sample_indices(n, seed + i)
         ops, got = V.request_host_bits(pool, arena, r, m, idx)
         want = orc.eval_program(cat[tree], ops, [alpha], dt)
         ok = np.array_equal(np.ascontiguousarray(got).view(BITS[dt]), want.view(BITS[dt]))
@@ -78,7 +79,7 @@ def test_served_equals_oracle_and_alone(pool, orc):
     assert len(batches) > 1                       # work was split into several launches
     assert all(r.status == 0 for r in res)
     # every element of every output against the oracle
-    assert check_against_oracle(orc, pool, arena, res, meta) == sum(m[2] for m in meta)
+    assert check_against_oracle(orc, pool, arena, res, meta, full=True) == sum(m[2] for m in meta)
     for i, (r, m) in enumerate(zip(res, meta)):
         got = served_bytes(arena, r, m)
         want = alone_bytes(pool, m)
