@@ -114,6 +114,28 @@ size_t salt_reduce_workspace_bytes(int64_t n, salt_dtype dtype);
 salt_status salt_dot(int64_t n, const void *x, const void *y, void *result,
                      void *workspace, size_t ws_bytes, salt_dtype dtype, void *hip_stream);
 
+/* salt_dot without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc. Same arguments (minus the workspace), same
+ * summation order and accumulation, and so the same result bits as
+ * salt_dot. The tile partials go to a buffer inside the library: a
+ * SALT_NOALLOC_MAX_PARTIALS-double (1 MiB) array on each GPU the library
+ * runs on, held until the process ends. The call allocates nothing.
+ *  - n may need at most SALT_NOALLOC_MAX_PARTIALS tiles, i.e.
+ *    salt_reduce_workspace_bytes(n, dtype) <= 1 MiB: n <= 2^30 (F64),
+ *    2^31 (F32), 2^32 (BF16/F16); beyond that SALT_ERR_UNSUPPORTED, before
+ *    anything is enqueued.
+ *  - Every call on one GPU shares that GPU's buffer, which keeps the last
+ *    call's partials (pass 1 overwrites every partial that pass 2 reads, so
+ *    nothing needs clearing). Calls that may overlap in time on one GPU
+ *    (different streams with no ordering between them, or threads) race and
+ *    give wrong results; calls ordered on one stream are safe.
+ *  - The first call on a GPU looks up that GPU's buffer address with that
+ *    GPU current (hipGetSymbolAddress); a failure there is SALT_ERR_DEVICE. */
+#define SALT_NOALLOC_MAX_PARTIALS 131072
+salt_status salt_dot_noalloc(int64_t n, const void *x, const void *y, void *result,
+                             salt_dtype dtype, void *hip_stream);
+
 /* Euclidean norm sqrt(sum_i x[i]^2), unscaled (the paper's "norm", Sec. 2),
  * with the same summation order, accumulation and arguments as salt_dot. */
 salt_status salt_nrm2(int64_t n, const void *x, void *result,

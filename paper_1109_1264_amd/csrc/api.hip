@@ -481,6 +481,42 @@ salt_status tuned_config(int kind, int route, int dtype, int64_t n, salt_launch_
 
 }  // namespace salt
 
+// ---- dot without a caller workspace -----------------------------------------
+// The tile partials of salt_dot_noalloc live in this file-scope array, one
+// copy per GPU, for the life of the process. Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in): the device
+// address of each GPU's copy is looked up once, with that GPU current, and
+// that address is what the launches receive.
+namespace salt {
+constexpr int64_t kNoallocPartials = SALT_NOALLOC_MAX_PARTIALS;
+static __device__ __align__(256) double scratch[kNoallocPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's `scratch`, looked up on first use.
+salt_status scratch_for_current_device(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(SALT_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SALT_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SALT_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SALT_OK;
+}
+}  // namespace
+}  // namespace salt
+
 extern "C" {
 
 salt_status salt_eval(const uint32_t *prog, int32_t prog_len, const void *const *operands,
@@ -519,6 +555,26 @@ int64_t salt_reduce_tile_elems(salt_dtype dtype) { return reduce_tile_elems(dtyp
 salt_status salt_dot(int64_t n, const void *x, const void *y, void *result, void *workspace,
                      size_t ws_bytes, salt_dtype dtype, void *hip_stream) {
     return reduce_impl(n, x, y, result, workspace, ws_bytes, dtype, hip_stream, nullptr, kModeDot);
+}
+
+salt_status salt_dot_noalloc(int64_t n, const void *x, const void *y, void *result, salt_dtype dtype,
+                             void *hip_stream) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    if (n < 0) return fail(SALT_ERR_ARG, "negative length");
+    const size_t need = salt_reduce_workspace_bytes(n, dtype);
+    if (need > (size_t)kNoallocPartials * sizeof(double))
+        return fail(SALT_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " needs " + std::to_string(need / 8) +
+                                              " tile partials; the built-in buffer holds " +
+                                              std::to_string(kNoallocPartials));
+    void *ws = nullptr;
+    if (need > 0) {
+        // argument errors first, so a rejected call touches no HIP state
+        if (!result) return fail(SALT_ERR_ARG, "result pointer is NULL");
+        if (!x || !y) return fail(SALT_ERR_ARG, "input pointer is NULL");
+        salt_status s = scratch_for_current_device(&ws);
+        if (s != SALT_OK) return s;
+    }
+    return reduce_impl(n, x, y, result, ws, need, dtype, hip_stream, nullptr, kModeDot);
 }
 
 salt_status salt_dot_ex(int64_t n, const void *x, const void *y, void *result, void *workspace,

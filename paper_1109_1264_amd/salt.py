@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         "salt_reduce_tile_elems": ([I32], I64),
         "salt_dot": ([I64, P, P, P, P, SZ, I32, P], I32),
         "salt_dot_ex": ([I64, P, P, P, P, SZ, I32, P, CFG], I32),
+        "salt_dot_noalloc": ([I64, P, P, P, I32, P], I32),
         "salt_nrm2": ([I64, P, P, P, SZ, I32, P], I32),
         "salt_nrm2_ex": ([I64, P, P, P, SZ, I32, P, CFG], I32),
         "salt_reduce_partials": ([I32, I64, P, P, P, I32, P], I32),
@@ -262,6 +263,20 @@ def salt_dot(x, y, n: int | None = None, result=None, ws=None, stream=None, conf
     else:
         st = L.salt_dot_ex(n, _dev(x), _dev(y), _dev(result), _dev(ws), nb, d, _stream_ptr(stream), _cfg(config))
     check(st)
+    return result
+
+
+def salt_dot_noalloc(x, y, n: int | None = None, result=None, stream=None):
+    """salt_dot with the library's own partials buffer (no workspace)."""
+    d = dtype_code(x)
+    if dtype_code(y) != d:
+        raise TypeError("x and y must share a dtype")
+    if n is None:
+        n = x.numel()
+    if x.numel() < n or y.numel() < n:
+        raise ValueError("tensor shorter than n")
+    result = _result_tensor(d, x.device) if result is None else result
+    check(lib().salt_dot_noalloc(n, _dev(x), _dev(y), _dev(result), d, _stream_ptr(stream)))
     return result
 
 
