@@ -14,6 +14,10 @@ timed region.
 The same JSON line also reports the whole size sweep and the three systems
 layers beside the plain binary64 kernels (each measured after the timed
 step):
+    mix:       each read/write mix (1..6 reads with one write; 1, 2, 3, 5
+               reads alone) on 2^28 binary64 elements: a plain stream
+               reference kernel beside the library kernel with that mix; the
+               5-read 1-write reference is the roofline's mix ceiling;
     sweep:     axpy, dot, nrm2 and the 5-operand tree for n = 2^10 .. 2^28 in
                binary64 and binary32 (device time per launch, GB/s, % of
                8 TB/s, % of the copy tree's rate at the same n, and whether
@@ -36,7 +40,7 @@ step):
                on sampled elements (served_parity_ok).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
-                    [--sections main,sweep,fusion,precision,blas1,batched,served]
+                    [--sections main,mix,sweep,fusion,precision,blas1,batched,served]
 """
 from __future__ import annotations
 
@@ -419,6 +423,59 @@ def section_sweep(args):
         del a, b, c, e, f, d, ws
         torch.cuda.empty_cache()
     return out
+
+
+# ---------------------------------------------------------------------------
+# read/write mix: the plain stream reference beside the library's kernels
+# ---------------------------------------------------------------------------
+
+def section_mix(args):
+    """Bandwidth of each read/write mix on binary64 arrays of 2^28 elements
+    (2 GiB each, HBM-resident): the plain stream reference (one 16-byte
+    chunk per lane, integer xor, no loop) against the library kernel with
+    the same mix (catalogue trees reading k operands and writing one; dot,
+    nrm2 and nrm2 of a sum of 3 or 5 operands, reading only). The reference
+    at 5 reads and 1 write is the ceiling the fused 5-operand tree is held
+    to."""
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    n = 1 << args.log2n
+    log("bench: read/write mix, n = 2^%d binary64" % args.log2n)
+    ins = workloads.uniform_device(n, "f64", workloads.sweep_seed(n) + 3, 6)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    ws = salt.workspace(n, salt.F64)
+    r = torch.empty(1, dtype=torch.float64, device="cuda")
+    cat = dict(salt.salt_catalogue())
+    lib = {(1, 1): ("copy", lambda: salt.salt_eval(cat["copy"], ins[:1], [], out)),
+           (2, 1): ("axpy tree", lambda: salt.salt_eval(cat["axpy"], ins[:2], [1.25], out)),
+           (3, 1): ("fig1 tree", lambda: salt.salt_eval(cat["fig1"], ins[:3], [], out)),
+           (4, 1): ("t4 tree", lambda: salt.salt_eval(cat["t4"], ins[:4], [1.25], out)),
+           (5, 1): ("tree5", lambda: salt.salt_eval(cat["tree5"], ins[:5], [], out)),
+           (6, 1): ("t5 tree", lambda: salt.salt_eval(cat["t5"], ins[:6], [1.25], out)),
+           (1, 0): ("nrm2", lambda: salt.salt_nrm2(ins[0], result=r, ws=ws)),
+           (2, 0): ("dot", lambda: salt.salt_dot(ins[0], ins[1], result=r, ws=ws)),
+           (3, 0): ("nrm2(a+b+c)", lambda: salt.salt_nrm2_expr(sum_prog(3), ins[:3], [], result=r, ws=ws)),
+           (5, 0): ("nrm2(a+b+c+e+f)", lambda: salt.salt_nrm2_expr(sum_prog(5), ins[:5], [], result=r, ws=ws))}
+    rows = []
+    for (R, W), (name, fn) in lib.items():
+        nbytes = (R + W) * 8 * n
+        t_ref = event_ms(lambda: salt.salt_stream_reference(ins[:R], out if W else None), 6)
+        t_lib = event_ms(fn, 6)
+        g_ref = nbytes / (t_ref * 1e-3) / 1e9
+        g_lib = nbytes / (t_lib * 1e-3) / 1e9
+        rows.append([R, W, round(t_ref, 4), round(g_ref, 1), round(100 * g_ref / HBM_PEAK_GBPS, 1), name,
+                     round(t_lib, 4), round(g_lib, 1), round(g_lib / g_ref, 3)])
+    del ins, out, ws
+    torch.cuda.empty_cache()
+    return {"n": n, "dtype": "f64",
+            "reference": "salt_stream_reference: one 16-byte chunk per lane, integer xor of the inputs, "
+                         "non-temporal loads and stores, no loop",
+            "columns": ["reads", "writes", "ref_ms", "ref_GBps", "ref_pct_of_8TBps", "library_kernel",
+                        "lib_ms", "lib_GBps", "lib_over_ref"],
+            "rows": rows}
 
 
 # ---------------------------------------------------------------------------
@@ -826,13 +883,73 @@ def served_parity(V, pool, arena, table, rate, count):
             "ok": not bad}
 
 
+def sum_prog(k: int) -> list:
+    """Postfix program of op0 + op1 + ... + op(k-1), left to right."""
+    import paper_1109_1264_amd.salt as salt
+
+    p = [salt.token(salt.LOAD, 0)]
+    for j in range(1, k):
+        p += [salt.token(salt.LOAD, j), salt.token(salt.ADD)]
+    return p
+
+
+def launch_only(args) -> None:
+    """Launch the named kernels --steps times each and print nothing else
+    (for counter collection under rocprofv3). Each spec is
+    kind:dtype:log2n, kind one of dot, nrm2 (whole call), dot1, nrm21 (pass 1
+    only), rsum3, rsum5 (nrm2 of the sum of 3 or 5 operands: 3 or 5 read
+    streams and no write), tree5, fig1, axpy, t4, t5, copy (catalogue trees
+    writing a fresh output). Inputs cycle through enough copies that each
+    launch reads past the 256 MiB last-level cache."""
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    cat = dict(salt.salt_catalogue())
+    codes = {"f64": salt.F64, "f32": salt.F32, "bf16": salt.BF16, "f16": salt.F16}
+    for spec in args.launch_only.split(","):
+        kind, dt, l2 = spec.split(":")
+        n = 1 << int(l2)
+        es = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[dt]
+        loads = {"dot": 2, "dot1": 2, "nrm2": 1, "nrm21": 1, "rsum3": 3, "rsum5": 5}.get(kind)
+        if loads is None:
+            loads = 1 + max(t >> 8 for t in cat[kind] if t & 0xFF == salt.LOAD)
+        set_bytes = loads * es * n
+        sets = max(2, min(8, -(-(1 << 30) // set_bytes)))
+        ops = [workloads.uniform_device(n, dt, workloads.sweep_seed(n) + k, loads) for k in range(sets)]
+        code = codes[dt]
+        ws = salt.workspace(n, code)
+        part = torch.empty(max(1, salt.salt_reduce_workspace_bytes(n, code) // 8), dtype=torch.float64,
+                           device="cuda")
+        out = torch.empty(n, dtype=ops[0][0].dtype, device="cuda") if kind in cat else None
+        for s in range(args.steps):
+            v = ops[s % sets]
+            if kind == "dot":
+                salt.salt_dot(v[0], v[1], ws=ws)
+            elif kind == "nrm2":
+                salt.salt_nrm2(v[0], ws=ws)
+            elif kind == "dot1":
+                salt.salt_reduce_partials(salt.MODE_DOT, v[0], v[1], partials=part)
+            elif kind == "nrm21":
+                salt.salt_reduce_partials(salt.MODE_NRM2, v[0], partials=part)
+            elif kind in ("rsum3", "rsum5"):
+                salt.salt_nrm2_expr(sum_prog(loads), v, [], ws=ws)
+            else:
+                salt.salt_eval(cat[kind], v, [1.25], out)
+        torch.cuda.synchronize()
+        log("bench: launched %s x%d" % (spec, args.steps))
+        del ops, ws, part, out
+        torch.cuda.empty_cache()
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--sections", default="main,sweep,fusion,precision,blas1,batched,served")
+    ap.add_argument("--sections", default="main,mix,sweep,fusion,precision,blas1,batched,served")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-log2n", type=int, default=26)
@@ -842,6 +959,9 @@ def main() -> int:
     ap.add_argument("--kernels-only", default=None,
                     help="comma list of tree5,axpy,dot,nrm2,copy: launch only these, --steps times "
                          "each, and print nothing (for counter collection)")
+    ap.add_argument("--launch-only", default=None,
+                    help="comma list of kind:dtype:log2n (see launch_only): launch only these, --steps "
+                         "times each, and print nothing (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -859,8 +979,20 @@ def main() -> int:
     if args.kernels_only:
         section_main(args, out)
         return 0
+    if args.launch_only:
+        launch_only(args)
+        return 0
     if "main" in sections:
         section_main(args, out)
+    if "mix" in sections:
+        out["mix"] = section_mix(args)
+        ref51 = [r for r in out["mix"]["rows"] if r[0] == 5 and r[1] == 1][0]
+        if out.get("roofline"):
+            ach = out["roofline"]["achieved"]
+            out["roofline"]["mix_ceiling"] = {
+                "GBps": ref51[3], "frac_of_peak": round(ref51[3] / HBM_PEAK_GBPS, 4),
+                "what": "plain 5-read 1-write stream reference on the same GPU (bench section mix)"}
+            out["roofline"]["frac_of_mix_ceiling"] = round(ach / ref51[3], 4)
     if "sweep" in sections:
         out["sweep"] = section_sweep(args)
     if "fusion" in sections:

@@ -431,6 +431,19 @@ const char *salt_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t salt_version(void);
 
+/* Measurement reference, not part of the method: the plainest stream with
+ * `reads` input arrays and `writes` output arrays (0 or 1) of `bytes` bytes
+ * each. One 16-byte chunk per lane, no loop, integer xor of the inputs (no
+ * floating point), non-temporal loads and stores. Its bandwidth for a given
+ * read/write mix is what the fused-evaluation kernels are measured against
+ * (a tree reading k operands and writing one result has the k-read,
+ * 1-write mix). The output holds the xor of the inputs; with writes == 0
+ * nothing is written and output may be NULL.
+ *  reads 1..6; bytes >= 0 and a multiple of 16; inputs (host array of
+ *  `reads` device pointers) and output 16-byte aligned. */
+salt_status salt_stream_reference(int32_t reads, int32_t writes, const void *const *inputs,
+                                  void *output, int64_t bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libsalt.so")
 
 HIP_SOURCES = ["batch_f64.hip", "batch_f32.hip", "batch_bf16.hip", "batch_f16.hip",
                "reduce_f64.hip", "reduce_f32.hip", "reduce_bf16.hip", "reduce_f16.hip",
-               "eval.hip", "reduce.hip", "batch.hip", "blas1.hip", "server.hip", "api.hip"]
+               "eval.hip", "reduce.hip", "batch.hip", "blas1.hip", "server.hip", "stream_ref.hip", "api.hip"]
 CXX_SOURCES = ["program.cpp"]
 ARCH = "gfx950"
 

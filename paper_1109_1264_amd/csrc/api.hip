@@ -750,6 +750,14 @@ salt_status salt_nrm2_expr_ex(const uint32_t *prog, int32_t prog_len, const void
                             workspace, ws_bytes, dtype, hip_stream, true, cfg);
 }
 
+salt_status salt_stream_reference(int32_t reads, int32_t writes, const void *const *inputs, void *output,
+                                  int64_t bytes, void *hip_stream) {
+    std::string why;
+    const salt_status s = stream_reference_impl(reads, writes, inputs, output, bytes, hip_stream, &why);
+    if (s != SALT_OK) return fail(s, why);
+    return SALT_OK;
+}
+
 salt_status salt_serve_trace(const salt_server_config *cfg, const salt_request *requests, int32_t count,
                              salt_request_result *results) {
     std::string why;

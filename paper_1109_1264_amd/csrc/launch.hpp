@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "program.hpp"
 #include "salt.h"
@@ -71,5 +72,10 @@ struct ReduceExprLaunch {
     void *stream;
 };
 hipError_t launch_reduce_expr(const ReduceExprLaunch &L, const Program &px, const Program *py, int dtype);
+
+// The plain read/write stream of salt_stream_reference (stream_ref.hip);
+// *err receives the message of a failure.
+salt_status stream_reference_impl(int32_t reads, int32_t writes, const void *const *inputs, void *output,
+                                  int64_t bytes, void *stream, std::string *err);
 
 }  // namespace salt

@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         "salt_dot": ([I64, P, P, P, P, SZ, I32, P], I32),
         "salt_dot_ex": ([I64, P, P, P, P, SZ, I32, P, CFG], I32),
         "salt_dot_noalloc": ([I64, P, P, P, I32, P], I32),
+        "salt_stream_reference": ([I32, I32, P, P, I64, P], I32),
         "salt_nrm2": ([I64, P, P, P, SZ, I32, P], I32),
         "salt_nrm2_ex": ([I64, P, P, P, SZ, I32, P, CFG], I32),
         "salt_reduce_partials": ([I32, I64, P, P, P, I32, P], I32),
@@ -278,6 +279,16 @@ def salt_dot_noalloc(x, y, n: int | None = None, result=None, stream=None):
     result = _result_tensor(d, x.device) if result is None else result
     check(lib().salt_dot_noalloc(n, _dev(x), _dev(y), _dev(result), d, _stream_ptr(stream)))
     return result
+
+
+def salt_stream_reference(inputs, out=None, nbytes: int | None = None, stream=None) -> None:
+    """The plain read/write stream of the same name (a bandwidth reference):
+    out = xor of the inputs, 16-byte chunks; out None reads only."""
+    if nbytes is None:
+        nbytes = inputs[0].numel() * inputs[0].element_size()
+    arr = (ctypes.c_void_p * len(inputs))(*[t.data_ptr() for t in inputs])
+    check(lib().salt_stream_reference(len(inputs), 0 if out is None else 1, arr,
+                                      None if out is None else _dev(out), nbytes, _stream_ptr(stream)))
 
 
 def salt_nrm2(x, n: int | None = None, result=None, ws=None, stream=None, config=None):

@@ -288,3 +288,19 @@ def test_sharded_reduction_argument_errors(L):
     assert L.salt_reduce_combine(0, P, 4, None, S.F64, None) == S.ERR_ARG
     assert L.salt_reduce_combine(0, None, 4, R, S.F64, None) == S.ERR_ARG
     assert L.salt_reduce_combine(0, P + 2, 4, R, S.F64, None) == S.ERR_ARG
+
+
+def test_stream_reference_argument_errors(L):
+    """The stream reference rejects bad shapes before any launch (fake
+    16-byte aligned addresses are never dereferenced)."""
+    fake = (ctypes.c_void_p * 6)(*([1 << 40] * 6))
+    out = ctypes.c_void_p(1 << 41)
+    assert L.salt_stream_reference(0, 1, fake, out, 64, None) == S.ERR_ARG      # no input
+    assert L.salt_stream_reference(7, 1, fake, out, 64, None) == S.ERR_ARG      # too many inputs
+    assert L.salt_stream_reference(2, 2, fake, out, 64, None) == S.ERR_ARG      # two outputs
+    assert L.salt_stream_reference(2, 1, fake, out, 40, None) == S.ERR_ARG      # not whole chunks
+    assert L.salt_stream_reference(2, 1, fake, out, -16, None) == S.ERR_ARG
+    assert L.salt_stream_reference(2, 1, fake, None, 64, None) == S.ERR_ARG     # output missing
+    odd = (ctypes.c_void_p * 2)((1 << 40) + 8, 1 << 40)
+    assert L.salt_stream_reference(2, 1, odd, out, 64, None) == S.ERR_ARG       # misaligned input
+    assert L.salt_stream_reference(2, 1, fake, out, 0, None) == S.OK           # nothing to do
