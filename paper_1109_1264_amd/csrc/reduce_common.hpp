@@ -61,7 +61,14 @@ struct AccExactProduct {
     float s = 0.0f, c = 0.0f;
     __device__ __forceinline__ void add(float x, float y) {
         float e;
-        two_sum(s, x * y, s, e);  // the product of two 16-bit values is exact
+        // The product of two binary16 values is exact in binary32 (11 + 11
+        // significant bits, exponents well inside binary32's range). A
+        // bfloat16 product (8 + 8 bits) is exact only while its magnitude
+        // lies in binary32's normal range: bfloat16 shares binary32's
+        // exponents, so a product below 2^-126 is rounded (to zero below
+        // 2^-149) and one above the largest binary32 overflows. Outside
+        // that range the result misses the stated error bound.
+        two_sum(s, x * y, s, e);
         c = c + e;
     }
     __device__ __forceinline__ double value() const { return (double)s + (double)c; }

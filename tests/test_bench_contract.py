@@ -48,3 +48,21 @@ def test_traffic_only_for_the_profiled_kernel_source():
         assert got == prof["traffic_bytes_per_launch"]
     else:
         assert got is None
+
+
+def test_traffic_is_derived_from_request_counts():
+    """The committed traffic figure is the request counts times their sizes
+    (128-byte reads, 64- or 32-byte writes), not a factor fitted to another
+    kernel, and it matches the algorithmic bytes of the tree kernel."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    with open(bench.PROFILE_PMC) as fh:
+        prof = json.load(fh)
+    c = prof["counters_per_launch"]
+    rd = 128 * (c["TCC_EA0_RDREQ_sum"] - c["TCC_EA0_RDREQ_32B_sum"]) + 32 * c["TCC_EA0_RDREQ_32B_sum"]
+    wr = 64 * c["TCC_EA0_WRREQ_64B_sum"] + 32 * (c["TCC_EA0_WRREQ_sum"] - c["TCC_EA0_WRREQ_64B_sum"])
+    assert prof["read_bytes_per_launch"] == rd and prof["write_bytes_per_launch"] == wr
+    assert prof["traffic_bytes_per_launch"] == rd + wr
+    assert abs(prof["traffic_bytes_per_launch"] / prof["algorithmic_bytes_per_launch"] - 1) < 1e-4
+    assert prof["algorithmic_bytes_per_launch"] == 48 * prof["n"]

@@ -140,3 +140,35 @@ def test_precision_workload_full_size(dtype):
     print("precision workload", dtype, n, flush=True)
     check_dot(dtype, x, y, gpu_dot(dx, dy))
     check_nrm2(dtype, x, gpu_nrm2(dx))
+
+
+def test_bf16_products_outside_the_normal_range(orc):
+    """The documented limits of the 16-bit accumulation: bfloat16 shares
+    binary32's exponent range, so a product below 2^-126 is rounded as a
+    binary32 subnormal (here (1 + 2^-7)^2 * 2^-140 keeps 9 significant bits:
+    (1 + 2^-6) * 2^-140), and a product above the largest binary32 gives a
+    non-finite result; binary16 products are exact."""
+    import math
+
+    import torch
+
+    def bf16_bits(v):
+        return np.array([orc.narrow(np.float32(v), "bf16")[0]] * 4, dtype=np.uint16)
+
+    x = bf16_bits((1 + 2.0 ** -7) * 2.0 ** -70)           # exactly representable in bfloat16
+    assert orc.widen(x, "bf16")[0] == (1 + 2.0 ** -7) * 2.0 ** -70
+    dx = to_dev(x, "bf16")
+    r = S.salt_dot(dx, dx)
+    torch.cuda.synchronize()
+    assert float(r.item()) == 4 * (1 + 2.0 ** -6) * 2.0 ** -140      # each product rounded
+    exact, _ = orc.dot2(orc.widen(x, "bf16"), orc.widen(x, "bf16"))
+    assert exact == 4 * (1 + 2.0 ** -6 + 2.0 ** -14) * 2.0 ** -140   # the oracle keeps every bit
+    big = to_dev(bf16_bits(2.0 ** 70), "bf16")
+    r = S.salt_dot(big, big)
+    torch.cuda.synchronize()
+    assert not math.isfinite(float(r.item()))
+    # binary16: the product of two half-precision values is exact in binary32
+    h = np.array([orc.narrow(np.float32(1 + 2.0 ** -10), "f16")[0]] * 4, dtype=np.uint16)
+    r = S.salt_dot(to_dev(h, "f16"), to_dev(h, "f16"))
+    torch.cuda.synchronize()
+    assert float(r.item()) == 4 * (1 + 2.0 ** -10) ** 2
