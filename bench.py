@@ -786,7 +786,36 @@ def section_batched(args):
         salt.salt_eval(abc, [a64, b64, c64], [1.25], d64)
         salt.salt_dot(a64, b64, result=r64, ws=ws64)
     t_64 = event_ms(plain64, 10)
-    res = {"instances": len(lengths), "elements": total, "tiles": bt.tiles,
+    # where the time goes: the same workload split into its whole tiles and
+    # its ragged last tiles (each as its own batch of items), and without
+    # the fused dot
+    T = salt.salt_reduce_tile_elems(salt.F32)
+
+    def sub_batch(lens, with_dot):
+        its = []
+        for k, n in enumerate(lens):
+            if n <= 0:
+                continue
+            s0 = int(offs[k])
+            its.append({"n": int(n), "operands": [a[s0:s0 + n], b[s0:s0 + n], c[s0:s0 + n]],
+                        "scalars": [float(alphas[k])], "out": d[s0:s0 + n],
+                        "dot_out": dots[k:k + 1] if with_dot else None})
+        sb = Batch(abc, its, salt.F32)
+        sg = sb.graph()
+        t = event_ms(sg.launch, 20)
+        el = int(sum(int(n) for n in lens if n > 0))
+        r = {"items": len(its), "elements": el, "tiles": sb.tiles, "graph_ms": round(t, 4),
+             "graph_GBps": round((16 * el + (8 * sb.tiles if with_dot else 0)) / (t * 1e-3) / 1e9, 1)}
+        sg.close()
+        sb.close()
+        return r
+    whole_lens = [(int(n) // T) * T for n in lengths]
+    ragged_lens = [int(n) % T for n in lengths]
+    split = {"tile_elems": T,
+             "whole_tiles_only": sub_batch(whole_lens, True),
+             "ragged_tiles_only": sub_batch(ragged_lens, True),
+             "all_tiles_no_dot": sub_batch([int(n) for n in lengths], False)}
+    res = {"instances": len(lengths), "elements": total, "tiles": bt.tiles, "split": split,
            "length_stats": {"min": int(lengths.min()), "median": int(np.median(lengths)),
                             "max": int(lengths.max()), "sigma_ln": 1.5},
            "graph_ms": round(t_graph, 4), "graph_GBps": round(alg_bytes / (t_graph * 1e-3) / 1e9, 1),
@@ -817,13 +846,26 @@ def section_served(args):
     arena, table = V.default_buffers(arena_bytes=arena_gb << 30, table_bytes=64 << 20)
     out = {"pool_GB": args.pool_gb, "arena_GB": arena_gb, "trees": list(V.TREES),
            "dtype_mix": dict(V.MIX), "lengths": "log-uniform 2^8..2^24"}
-    # warm-up: the first call loads every batched kernel variant it meets
+    # warm-up: the first calls load every batched kernel variant they meet
+    # and touch the whole output arena
     trace, meta = V.make_trace(pool, 2000, seed=workloads.SEED_SERVED + 999, rate=None)
-    V.serve(trace, arena, table)
-    # saturation: every request present at t = 0
-    trace, meta = V.make_trace(pool, args.served_requests, seed=workloads.SEED_SERVED, rate=None)
-    sat = V.summarize(V.serve(trace, arena, table), meta)
+    for pol in (V.GROUP_MIXED, V.GROUP_BY_TREE):
+        V.serve(trace, arena, table, grouping=pol)
+    # saturation: every request present at t = 0; each grouping policy twice,
+    # interleaved, the better run of each kept
+    sat_trace, sat_meta = V.make_trace(pool, args.served_requests, seed=workloads.SEED_SERVED, rate=None)
+    V.serve(sat_trace, arena, table)
+    runs = {V.GROUP_AUTO: [], V.GROUP_MIXED: [], V.GROUP_BY_TREE: []}
+    for _ in range(2):
+        for pol in runs:
+            runs[pol].append(V.summarize(V.serve(sat_trace, arena, table, grouping=pol), sat_meta))
+    best = {pol: max(r, key=lambda s: s["throughput_rps"]) for pol, r in runs.items()}
+    sat = best[V.GROUP_MIXED]
     out["saturation"] = sat
+    out["saturation_by_grouping"] = {
+        name: {"best": best[pol], "runs_rps": [r["throughput_rps"] for r in runs[pol]]}
+        for name, pol in (("auto", V.GROUP_AUTO), ("always_mixed", V.GROUP_MIXED),
+                          ("always_by_tree", V.GROUP_BY_TREE))}
     rate_sat = sat["throughput_rps"]
     levels = {}
     for frac in (0.25, 0.5, 0.75, 0.9):
@@ -836,6 +878,12 @@ def section_served(args):
     trace, meta = V.make_trace(pool, args.served_requests, seed=workloads.SEED_SERVED + 50, rate=0.5 * rate_sat,
                                fp64_only=True, mix=(("f64", 1.0),))
     out["poisson_0.5_all_f64"] = V.summarize(V.serve(trace, arena, table), meta)
+    # the 0.9 stream under the other grouping policies (the levels above use
+    # one mixed-tree launch per element type)
+    trace, meta = V.make_trace(pool, args.served_requests, seed=workloads.SEED_SERVED + 90, rate=0.9 * rate_sat)
+    out["poisson_0.9_by_grouping"] = {
+        name: V.summarize(V.serve(trace, arena, table, grouping=pol), meta)
+        for name, pol in (("auto", V.GROUP_AUTO), ("always_by_tree", V.GROUP_BY_TREE))}
     if not args.no_parity:
         out["parity"] = served_parity(V, pool, arena, table, 0.5 * rate_sat, args.served_parity_requests)
         out["served_parity_ok"] = out["parity"]["ok"]

@@ -369,8 +369,9 @@ void salt_batch_plan_destroy(salt_batch_plan plan);
  * in device memory. Requests arrive over time (open loop, from a trace);
  * each is admitted when a slot is free and its output fits in the output
  * arena (first-fit; memory-based admission, FIFO order); admitted requests
- * are gathered into batched launches (one per tree and element type in the
- * batch) on one of several streams as soon as a stream can take more work,
+ * are gathered into batched launches (per element type in the batch, one
+ * launch with items of every tree mixed, or one launch per tree) on one of
+ * several streams as soon as a stream can take more work,
  * so requests that arrive while others run are admitted and overlap with
  * them on the device (continuous batching). Completion times are the GPU
  * events of the batch, mapped to the host clock. Everything runs on the
@@ -388,7 +389,13 @@ typedef struct {
     int32_t depth;           /* batches in flight per stream (1..4)           */
     int32_t release_on_complete; /* 1: free an output as soon as it completes;
                                   * 0: keep every output (results[i].out)    */
+    int32_t grouping;        /* launches of one batch, per element type:
+                              * 0 one mixed-tree launch; 1 one single-tree
+                              * launch per tree; 2 one per tree when the
+                              * type's requests in the batch hold at least
+                              * SALT_SERVE_SPLIT_ELEMS elements, else mixed */
 } salt_server_config;
+#define SALT_SERVE_SPLIT_ELEMS ((int64_t)1 << 26)
 
 typedef struct {
     double arrival_s;                       /* seconds from the start of the run */

@@ -822,6 +822,7 @@ salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len, int32
                 d.sc32[j] = (float)it.scalars[p.sc_map[j]];
             }
             d.vec = vec ? 1 : 0;
+            d.tree = pl->route;
             d.out = it.n > 0 ? it.out : nullptr;
             d.dot_out = it.dot_out;
             if (it.dot_out) {

@@ -14,7 +14,7 @@ struct alignas(16) DevItem {
     int64_t n;
     int64_t tile_begin;  // first global tile of this item
     int32_t vec;         // every array of the item is 16-byte aligned
-    int32_t pad0;
+    int32_t tree;        // catalogue id of the item's tree (mixed-tree launches)
     const void *ops[SALT_MAX_OPERANDS];
     double sc64[SALT_MAX_SCALARS];  // scalars rounded to binary64 ...
     float sc32[SALT_MAX_SCALARS];   // ... and to binary32 (once, on the host)
@@ -52,6 +52,9 @@ struct BatchLaunch {
 
 using BatchFn = int (*)(const BatchLaunch &);  // returns a hipError_t
 BatchFn catalogue_batch_launcher(int id, int dtype);
+// Launcher for items of any catalogue trees in one element type: each item
+// names its tree (DevItem::tree); element-wise evaluation only (no dot).
+BatchFn catalogue_batch_multi_launcher(int dtype);
 // Number of distinct operands the catalogue tree reads (-1: bad id).
 int catalogue_loads(int id);
 

@@ -189,17 +189,70 @@ __global__ __launch_bounds__(kBlock) void k_batch(const DevItem *__restrict__ it
         }
         Acc<DT> acc[V];
         const int64_t m = n - t * T;
+        // Streaming (non-temporal) accesses pay off on whole tiles; the short
+        // ragged tiles run faster with ordinary cached accesses (measured).
         if (!vec)
             batch_tile<E, DT, UR, NT, DOT, kUnaligned>(op, s, it.out, n, t, m, acc);
         else if (m >= T)
             batch_tile<E, DT, UR, NT, DOT, kWhole>(op, s, it.out, n, t, m, acc);
         else
-            batch_tile<E, DT, UR, NT, DOT, kRagged>(op, s, it.out, n, t, m, acc);
+            batch_tile<E, DT, UR, false, DOT, kRagged>(op, s, it.out, n, t, m, acc);
         if constexpr (DOT) {
             if (it.dot_out) {
                 const double v = block_sum<kBlock / 64>(lane_value<DT>(acc), lds);
                 if (threadIdx.x == 0) ws[it.tile_begin + t] = v;
             }
+        }
+    }
+}
+
+// Tile `t` of item `it` evaluated with the tree E (no dot): the item's
+// operands and scalars, then the tile form.
+template <class E, int DT, int UR, bool NT>
+__device__ __forceinline__ void eval_item_tile(const DevItem &it, int64_t t) {
+    using C = typename Tr<DT>::C;
+    constexpr int V = Tr<DT>::V;
+    constexpr int64_t T = tile_elems<DT>();
+    constexpr int NL = E::n_loads > 0 ? E::n_loads : 1;
+    constexpr int NS = E::n_scal > 0 ? E::n_scal : 1;
+    const int64_t n = it.n;
+    const void *op[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) op[q] = it.ops[q];
+    C s[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        if constexpr (DT == SALT_F64) s[j] = it.sc64[j];
+        else s[j] = it.sc32[j];
+    }
+    Acc<DT> unused[V];
+    const int64_t m = n - t * T;
+    if (!it.vec)
+        batch_tile<E, DT, UR, NT, false, kUnaligned>(op, s, it.out, n, t, m, unused);
+    else if (m >= T)
+        batch_tile<E, DT, UR, NT, false, kWhole>(op, s, it.out, n, t, m, unused);
+    else
+        batch_tile<E, DT, UR, false, false, kRagged>(op, s, it.out, n, t, m, unused);
+}
+
+// Items of different catalogue trees in one launch (one element type): the
+// tile list mixes the items' tiles, and each tile branches on its item's
+// tree. The branch is uniform over the workgroup (one tile per workgroup at
+// a time), so it costs a scalar compare, and a serving batch needs one
+// launch per element type instead of one per (tree, element type).
+template <int DT, int UR, bool NT>
+__global__ __launch_bounds__(kBlock) void k_batch_multi(const DevItem *__restrict__ items,
+                                                        const TileRef *__restrict__ tiles, int64_t total_tiles) {
+    for (int64_t gt = blockIdx.x; gt < total_tiles; gt += gridDim.x) {
+        const int k = __builtin_amdgcn_readfirstlane(tiles[gt].item);
+        const int64_t t = __builtin_amdgcn_readfirstlane(tiles[gt].tile);
+        const DevItem &it = items[k];
+        switch (__builtin_amdgcn_readfirstlane(it.tree)) {
+#define SALT_CAT_CASE(name, ...) \
+    case cat::id_##name: eval_item_tile<cat::name, DT, UR, NT>(it, t); break;
+            SALT_CATALOGUE(SALT_CAT_CASE)
+#undef SALT_CAT_CASE
+            default: break;
         }
     }
 }
@@ -255,6 +308,27 @@ static int launch_batch(const BatchLaunch &L) {
     return launch_batch_dot<E, DT, false>(L);
 }
 
+template <int DT, int UR, bool NT>
+static int launch_multi_u(const BatchLaunch &L) {
+    int64_t grid = L.blocks > 0 && L.blocks < L.total_tiles ? L.blocks : L.total_tiles;
+    if (grid > 0x7fffffff) grid = 0x7fffffff;
+    if (grid > 0)
+        hipLaunchKernelGGL((k_batch_multi<DT, UR, NT>), dim3((unsigned)grid), dim3(kBlock), 0,
+                           (hipStream_t)L.stream, L.items, L.tiles, L.total_tiles);
+    return (int)hipGetLastError();
+}
+
+// Mixed-tree launch: 2 or 4 chunks per burst (8 runs as 4: the six-operand
+// tree at 8 would need about 200 registers for its operand chunks alone).
+template <int DT>
+static int launch_batch_multi(const BatchLaunch &L) {
+    if (L.any_dot) return (int)hipErrorInvalidValue;
+    const bool nt = L.nontemporal != 0;
+    if (L.unroll == 2) return nt ? launch_multi_u<DT, 2, true>(L) : launch_multi_u<DT, 2, false>(L);
+    if (L.unroll == 4 || L.unroll == 8) return nt ? launch_multi_u<DT, 4, true>(L) : launch_multi_u<DT, 4, false>(L);
+    return (int)hipErrorInvalidValue;
+}
+
 // Launcher for catalogue tree `id` in element type DT (instantiated once per
 // type, in batch_<type>.hip).
 template <int DT>
@@ -272,5 +346,9 @@ BatchFn batch_launcher_f64(int id);
 BatchFn batch_launcher_f32(int id);
 BatchFn batch_launcher_bf16(int id);
 BatchFn batch_launcher_f16(int id);
+BatchFn batch_multi_launcher_f64();
+BatchFn batch_multi_launcher_f32();
+BatchFn batch_multi_launcher_bf16();
+BatchFn batch_multi_launcher_f16();
 
 }  // namespace salt

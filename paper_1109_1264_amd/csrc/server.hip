@@ -10,9 +10,13 @@
 //      output fits in the arena (first-fit allocator): memory-based
 //      admission;
 //   4. launch: when a stream can take another batch, every admitted request
-//      not yet launched (up to max_batch) is grouped by (tree, element type)
-//      and each group runs as one batched launch (batch.hip); the groups'
-//      descriptors travel in one copy from pinned staging memory.
+//      not yet launched (up to max_batch) is grouped by element type; a
+//      group runs as one batched launch of the mixed-tree kernel (each item
+//      names its tree; batch_kernels.hpp), or is split by tree into
+//      single-tree launches: always, never, or when the type's requests hold
+//      many elements (the single-tree kernels stream a little faster, one
+//      mixed launch finishes a small batch sooner); the groups' descriptors
+//      travel in one copy from pinned staging memory.
 // Requests that arrive while others run are admitted as slots and memory
 // free up and overlap with them on the device (continuous batching).
 #include <algorithm>
@@ -108,6 +112,7 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
     if (cfg->max_inflight < 1 || cfg->max_batch < 1) return bad("max_inflight and max_batch must be >= 1");
     if (cfg->n_streams < 1 || cfg->n_streams > 8) return bad("n_streams outside 1..8");
     if (cfg->depth < 1 || cfg->depth > 4) return bad("depth outside 1..4");
+    if (cfg->grouping < 0 || cfg->grouping > 2) return bad("grouping outside 0..2");
     const int n_slots = cfg->n_streams * cfg->depth;
     const size_t slot_cap = cfg->table_bytes / n_slots / kAlign * kAlign;
     if (slot_cap < 64 * 1024) return bad("table arena too small for the streams and depth");
@@ -276,12 +281,20 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                     admitted.pop_front();
                 }
                 if (take.empty()) goto idle;
-                // group by (tree, dtype), keeping admission order inside a group
-                std::stable_sort(take.begin(), take.end(), [&](int x, int y) {
-                    return std::make_pair(reqs[x].tree, reqs[x].dtype) < std::make_pair(reqs[y].tree, reqs[y].dtype);
-                });
+                // group by element type, and split a type's group by tree
+                // as the grouping policy says; admission order is kept
+                // inside a group
+                int64_t type_elems[SALT_F16 + 1] = {};
+                for (int r : take) type_elems[reqs[r].dtype] += reqs[r].n;
+                auto split = [&](int d) {
+                    return cfg->grouping == 1 || (cfg->grouping == 2 && type_elems[d] >= SALT_SERVE_SPLIT_ELEMS);
+                };
+                auto key = [&](int x) {
+                    return std::make_pair(reqs[x].dtype, split(reqs[x].dtype) ? reqs[x].tree : -1);
+                };
+                std::stable_sort(take.begin(), take.end(), [&](int x, int y) { return key(x) < key(y); });
                 struct Group {
-                    int tree, dtype;
+                    int dtype, tree;  // tree: -1 for a mixed-tree group
                     size_t items_off, map_off;
                     int count;
                     int64_t tiles, elems;
@@ -292,10 +305,8 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                 sl.group_of.clear();
                 for (size_t a = 0; a < take.size();) {
                     size_t b = a;
-                    while (b < take.size() && reqs[take[b]].tree == reqs[take[a]].tree &&
-                           reqs[take[b]].dtype == reqs[take[a]].dtype)
-                        ++b;
-                    Group g{reqs[take[a]].tree, reqs[take[a]].dtype, pos, 0, (int)(b - a), 0, 0};
+                    while (b < take.size() && key(take[b]) == key(take[a])) ++b;
+                    Group g{reqs[take[a]].dtype, key(take[a]).second, pos, 0, (int)(b - a), 0, 0};
                     const int64_t T = reduce_tile_elems(g.dtype);
                     DevItem *items = (DevItem *)(sl.staging + pos);
                     for (size_t j = a; j < b; ++j) {
@@ -304,6 +315,7 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                         std::memset(&d, 0, sizeof d);
                         d.n = r.n;
                         d.tile_begin = g.tiles;
+                        d.tree = r.tree;
                         bool vec = ((uintptr_t)res[take[j]].out & 15u) == 0;
                         const int nl = catalogue_loads(r.tree);
                         for (int k = 0; k < nl; ++k) {
@@ -337,12 +349,16 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                     return dev_fail(e);
                 for (size_t gi = 0; gi < groups.size(); ++gi) {
                     const Group &g = groups[gi];
+                    // knobs of the group's tree at its size; a mixed group
+                    // takes those of the batched five-operand tree (the
+                    // mixed-tree kernel runs 2 or 4 chunks per burst)
                     salt_launch_config c;
-                    if (tuned_config(3, g.tree, g.dtype, g.elems, &c) != SALT_OK) {
-                        c.unroll = 8;
+                    if (tuned_config(3, g.tree >= 0 ? g.tree : (int)cat::id_tree5, g.dtype, g.elems, &c) != SALT_OK) {
+                        c.unroll = 4;
                         c.nontemporal = 1;
                         c.blocks = 0;
                     }
+                    if (g.tree < 0 && c.unroll != 2) c.unroll = 4;
                     BatchLaunch L;
                     L.items = (const DevItem *)(sl.dev_table + g.items_off);
                     L.tiles = (const TileRef *)(sl.dev_table + g.map_off);
@@ -354,7 +370,8 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                     L.nontemporal = c.nontemporal;
                     L.blocks = c.blocks;
                     L.stream = s;
-                    BatchFn fn = catalogue_batch_launcher(g.tree, g.dtype);
+                    BatchFn fn = g.tree >= 0 ? catalogue_batch_launcher(g.tree, g.dtype)
+                                             : catalogue_batch_multi_launcher(g.dtype);
                     if (!fn) return dev_fail(hipErrorInvalidValue);
                     if ((e = (hipError_t)fn(L)) != hipSuccess) return dev_fail(e);
                     if ((e = hipEventRecord(sl.ev[gi], s)) != hipSuccess) return dev_fail(e);

@@ -31,7 +31,7 @@ class ServerConfig(ctypes.Structure):
                 ("table_arena", ctypes.c_void_p), ("table_bytes", ctypes.c_size_t),
                 ("max_inflight", ctypes.c_int32), ("n_streams", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("release_on_complete", ctypes.c_int32)]
+                ("release_on_complete", ctypes.c_int32), ("grouping", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -159,14 +159,21 @@ def request_host_bits(pool: Pool, arena, r, m, idx=None):
     return ops, host(out_view)
 
 
-def serve(trace, arena, table, max_inflight=4096, n_streams=4, max_batch=512, depth=2, keep_outputs=False):
-    """Run the trace through the native loop; returns the results array."""
+GROUP_MIXED, GROUP_BY_TREE, GROUP_AUTO = 0, 1, 2
+
+
+def serve(trace, arena, table, max_inflight=4096, n_streams=4, max_batch=512, depth=2, keep_outputs=False,
+          grouping=GROUP_MIXED):
+    """Run the trace through the native loop; returns the results array.
+    Per element type a batch runs one mixed-tree launch (GROUP_MIXED), one
+    single-tree launch per tree (GROUP_BY_TREE), or the latter only when the
+    type's requests hold at least 2^26 elements (GROUP_AUTO)."""
     L = _declare()
     count = len(trace)
     res = (RequestResult * max(1, count))()
     cfg = ServerConfig(arena.data_ptr(), arena.numel() * arena.element_size(), table.data_ptr(),
                        table.numel() * table.element_size(), max_inflight, n_streams, max_batch, depth,
-                       0 if keep_outputs else 1)
+                       0 if keep_outputs else 1, grouping)
     S.check(L.salt_serve_trace(ctypes.byref(cfg), trace, count, res))
     return res
 

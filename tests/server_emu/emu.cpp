@@ -118,7 +118,8 @@ static void exec_kernel(Op &op) {
         if (!seen.insert({r.item, r.tile}).second) ERR("tile listed twice");
         // address ranges one tile touches (elements [t*T, min(n, (t+1)*T)))
         const uint64_t lo = (uint64_t)r.tile * T, hi = std::min<uint64_t>(it.n, lo + T);
-        const int nl = loads_of(op.tree);
+        const int nl = loads_of(op.tree >= 0 ? op.tree : it.tree);
+        if (op.tree < 0 && (it.tree < 0 || it.tree > 7)) ERR("item names no catalogue tree");
         for (int q = 0; q < nl; ++q) {
             const uint64_t a = (uint64_t)it.ops[q] + lo * es, b = (uint64_t)it.ops[q] + hi * es;
             bool ok = false;
@@ -291,11 +292,17 @@ BatchFn catalogue_batch_launcher(int id, int dtype) {
     g_dtype = dtype;
     return &stub_launch;
 }
+BatchFn catalogue_batch_multi_launcher(int dtype) {
+    g_tree = -1;  // each item names its tree
+    g_dtype = dtype;
+    return &stub_launch;
+}
 }  // namespace salt
 
 int main(int argc, char **argv) {
-    if (argc != 9) {
-        std::fprintf(stderr, "usage: emu pool.txt trace.bin arena_gb p_step seed max_batch n_streams depth\n");
+    if (argc != 9 && argc != 10) {
+        std::fprintf(stderr,
+                     "usage: emu pool.txt trace.bin arena_gb p_step seed max_batch n_streams depth [grouping]\n");
         return 2;
     }
     FILE *f = std::fopen(argv[1], "r");
@@ -332,6 +339,7 @@ int main(int argc, char **argv) {
     cfg.max_batch = max_batch;
     cfg.depth = depth;
     cfg.release_on_complete = 1;
+    cfg.grouping = argc == 10 ? std::atoi(argv[9]) : 0;
     std::vector<salt_request_result> res(reqs.size());
     std::string err;
     const salt_status s = salt::serve_trace_impl(&cfg, reqs.data(), (int32_t)reqs.size(), res.data(), &err);

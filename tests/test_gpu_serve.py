@@ -68,12 +68,13 @@ def served_bytes(arena, r, m):
     return arena.view(__import__("torch").uint8)[off:off + m[2] * ES[m[1]]]
 
 
-def test_served_equals_oracle_and_alone(pool, orc):
+@pytest.mark.parametrize("grouping", [V.GROUP_MIXED, V.GROUP_BY_TREE, V.GROUP_AUTO])
+def test_served_equals_oracle_and_alone(pool, orc, grouping):
     import torch
 
     arena, table = V.default_buffers(arena_bytes=1 << 30, table_bytes=16 << 20)
     trace, meta = V.make_trace(pool, 400, seed=5001, rate=20000.0, lo=8, hi=17)
-    res = V.serve(trace, arena, table, n_streams=3, max_batch=64, keep_outputs=True)
+    res = V.serve(trace, arena, table, n_streams=3, max_batch=64, keep_outputs=True, grouping=grouping)
     torch.cuda.synchronize()
     batches = {r.batch for r in res}
     assert len(batches) > 1                       # work was split into several launches
@@ -126,6 +127,8 @@ def test_bad_config_is_rejected(pool):
     assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # 9 streams
     cfg = V.ServerConfig(arena.data_ptr(), 1 << 20, table.data_ptr(), 1 << 10, 16, 2, 8, 1, 1)
     assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # table too small
+    cfg = V.ServerConfig(arena.data_ptr(), 1 << 20, table.data_ptr(), 4 << 20, 16, 2, 8, 1, 1, 3)
+    assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # grouping 3
 
 
 def test_waits_for_callers_queued_work(pool, orc):

@@ -81,17 +81,19 @@ def setup(tmp_path_factory):
     return tmp, build(tmp, os.path.join(CSRC, "server.hip")), traces
 
 
-def run(exe, tmp, trace, arena_gb, p, seed, max_batch=512, streams=4, depth=2):
+def run(exe, tmp, trace, arena_gb, p, seed, max_batch=512, streams=4, depth=2, grouping=0):
     return subprocess.run([exe, os.path.join(tmp, "pool.txt"), trace, str(arena_gb), str(p), str(seed),
-                           str(max_batch), str(streams), str(depth)], capture_output=True, text=True, timeout=300)
+                           str(max_batch), str(streams), str(depth), str(grouping)], capture_output=True, text=True,
+                          timeout=300)
 
 
+@pytest.mark.parametrize("grouping", [0, 1, 2])
 @pytest.mark.parametrize("trace", ["warm", "saturation", "poisson", "f64"])
-def test_loop_tables_tiles_and_addresses(setup, trace):
+def test_loop_tables_tiles_and_addresses(setup, trace, grouping):
     tmp, exe, traces = setup
     for arena_gb, p, seed, mb, ns, dp in ((32, 0.3, 1, 512, 4, 2), (8, 0.05, 2, 512, 4, 2), (32, 1.0, 3, 128, 8, 4),
                                           (4, 0.02, 4, 2048, 2, 1)):
-        r = run(exe, tmp, traces[trace], arena_gb, p, seed, mb, ns, dp)
+        r = run(exe, tmp, traces[trace], arena_gb, p, seed, mb, ns, dp, grouping)
         assert r.returncode == 0, (trace, arena_gb, p, seed, r.stdout, r.stderr[-2000:])
 
 
