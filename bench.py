@@ -539,6 +539,55 @@ def section_fusion(args):
     del a, b, c, e, d, t, ws
     torch.cuda.empty_cache()
     out["fig1_n2p20"] = fig1_small()
+    out["expression_reductions"] = expression_reductions(args)
+    return out
+
+
+def expression_reductions(args):
+    """Trees reduced without being written (Sec. 2's lazy evaluation inside
+    a dot product or a norm), n = 2^28, by storage type: the pairs with
+    ahead-of-time kernels against the interpreter running an equivalent
+    pair (b + a for a + b: the same bits), and the same bits checked."""
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    T = salt.token
+    L0, L1, S0 = T(salt.LOAD, 0), T(salt.LOAD, 1), T(salt.SCALAR, 0)
+    n = 1 << args.log2n
+    cases = {"dot(a+b, a-b)": (([L0, L1, T(salt.ADD)], [L0, L1, T(salt.SUB)]),
+                               ([L1, L0, T(salt.ADD)], [L0, L1, T(salt.SUB)])),
+             "nrm2(alpha*a + b)": (([S0, L0, T(salt.MUL), L1, T(salt.ADD)], None),
+                                   ([L1, S0, L0, T(salt.MUL), T(salt.ADD)], None))}
+    out = {"n": n, "bytes": "2 operands read once: 2 s bytes per element"}
+    for dt in ("f64", "f32", "bf16"):
+        code = {"f64": salt.F64, "f32": salt.F32, "bf16": salt.BF16}[dt]
+        es = {"f64": 8, "f32": 4, "bf16": 2}[dt]
+        log("bench: expression reductions, %s" % dt)
+        a, b = workloads.uniform_device(n, dt, workloads.sweep_seed(n) + 4, 2)
+        ws = salt.workspace(n, code)
+        rdt = torch.float64 if dt == "f64" else torch.float32
+        r1 = torch.empty(1, dtype=rdt, device="cuda")
+        r2 = torch.empty(1, dtype=rdt, device="cuda")
+        rows = {}
+        for name, ((px, py), (qx, qy)) in cases.items():
+            def run(p, q, r):
+                if q is None:
+                    salt.salt_nrm2_expr(p, [a, b], [1.375], result=r, ws=ws)
+                else:
+                    salt.salt_dot_expr(p, q, [a, b], [1.375], result=r, ws=ws)
+            t_aot = event_ms(lambda: run(px, py, r1), 10)
+            t_int = event_ms(lambda: run(qx, qy, r2), 10)
+            torch.cuda.synchronize()
+            gb = lambda t: round(2 * es * n / (t * 1e-3) / 1e9, 1)
+            rows[name] = {"ahead_of_time_ms": round(t_aot, 4), "ahead_of_time_GBps": gb(t_aot),
+                          "ahead_of_time_pct_of_8TBps": round(100 * 2 * es * n / (t_aot * 1e-3) / 8e12, 1),
+                          "interpreter_ms": round(t_int, 4), "interpreter_GBps": gb(t_int),
+                          "same_bits": bool(torch.equal(r1, r2))}
+        out[dt] = rows
+        del a, b, ws
+        torch.cuda.empty_cache()
     return out
 
 

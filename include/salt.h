@@ -421,6 +421,17 @@ typedef struct {
 salt_status salt_serve_trace(const salt_server_config *cfg, const salt_request *requests,
                              int32_t count, salt_request_result *results);
 
+/* Which kernel salt_dot_expr (prog_y non-NULL) or salt_nrm2_expr (prog_y
+ * NULL) runs for these programs, without touching the GPU: *route is the
+ * index of the pair in the library's catalogue of reduction pairs with
+ * ahead-of-time kernels (dot(a + b, a - b), nrm2(a - b), nrm2(alpha*a + b),
+ * with any operand and scalar numbering; a dot also with its two programs
+ * exchanged), or -1 for the interpreter. Both give the same bits. Programs
+ * are validated as in those calls. */
+salt_status salt_reduce_expr_route(const uint32_t *prog_x, int32_t len_x,
+                                   const uint32_t *prog_y, int32_t len_y,
+                                   int32_t n_operands, int32_t n_scalars, int32_t *route);
+
 /* Validate a program without touching the GPU. On success fills
  * *stack_need (maximum stack depth) and *n_loads (distinct operands read)
  * when those pointers are non-null. */

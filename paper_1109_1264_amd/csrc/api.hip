@@ -72,6 +72,30 @@ const std::vector<CatEntry> &catalogue() {
     return v;
 }
 
+// Reduction pairs with ahead-of-time kernels: each entry's P and Q tokens in
+// canonical numbering (expr.hpp, SALT_RCATALOGUE).
+struct RcatEntry {
+    int lp, lq;
+    uint32_t p[SALT_MAX_TOKENS], q[SALT_MAX_TOKENS];
+};
+
+const std::vector<RcatEntry> &rcatalogue() {
+    static const std::vector<RcatEntry> v = [] {
+        std::vector<RcatEntry> r;
+#define SALT_RCAT_EMIT(name)           \
+    {                                  \
+        RcatEntry e{};                 \
+        rcat::name::P::emit(e.p, e.lp); \
+        rcat::name::Q::emit(e.q, e.lq); \
+        r.push_back(e);                \
+    }
+        SALT_RCATALOGUE(SALT_RCAT_EMIT)
+#undef SALT_RCAT_EMIT
+        return r;
+    }();
+    return v;
+}
+
 int route_of(const Program &p) {
     const auto &c = catalogue();
     for (size_t i = 0; i < c.size(); ++i)
@@ -82,6 +106,9 @@ int route_of(const Program &p) {
 
 // ---- tuning table ------------------------------------------------------------
 enum Kind { kEval = 0, kDot = 1, kNrm2 = 2, kBatch = 3 };
+// Tuning-table routes: catalogue trees 0.., the interpreter -1, expression
+// reductions on the interpreter -2, reduction pair id at kRouteRcat0 - id.
+constexpr int kRouteRcat0 = -16;
 
 struct TuneRow {
     int kind, route, dtype, log2n;
@@ -454,8 +481,34 @@ salt_status reduce_expr_impl(const uint32_t *px, int32_t lx, const uint32_t *py,
         if (ws_bytes < need) return fail(SALT_ERR_WORKSPACE, "workspace too small");
     }
     for (int j = 0; j < n_scalars && j < SALT_MAX_SCALARS; ++j) L.sc[j] = scalars ? scalars[j] : 0.0;
-    // Tuned knobs of the expression reductions live under route -2.
+    // A pair with an ahead-of-time kernel runs it (same bits as the
+    // interpreter); its tuned knobs live under route kRouteRcat0 - id.
+    int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
+    const int rid = route_pair(px, lx, nrm2 ? nullptr : py, nrm2 ? 0 : ly, om, sm);
     salt_launch_config c;
+    if (rid >= 0) {
+        int nl = 0;
+        for (int k = 0; k < SALT_MAX_OPERANDS; ++k) nl += (mask >> k) & 1u;
+        s = resolve(cfg, lookup(nrm2 ? kNrm2 : kDot, kRouteRcat0 - rid, dtype, n, nl), nrm2 ? kNrm2 : kDot, &c);
+        if (s != SALT_OK) return s;
+        ReduceExprLaunch R;
+        std::memset(&R, 0, sizeof R);
+        for (int k = 0; k < nl; ++k) R.ops[k] = operands[om[k]];
+        const int nsc = gx.n_scal > (nrm2 ? 0 : gy.n_scal) ? gx.n_scal : gy.n_scal;
+        for (int j = 0; j < nsc && j < SALT_MAX_SCALARS; ++j) R.sc[j] = scalars[sm[j]];
+        R.result = result;
+        R.ws = (double *)ws;
+        R.n = n;
+        R.vec = vec ? 1 : 0;
+        R.unroll = c.unroll;
+        R.nontemporal = c.nontemporal;
+        R.blocks = c.blocks;
+        R.nrm2 = nrm2 ? 1 : 0;
+        R.stream = stream;
+        return device_status(launch_reduce_tree(R, rid, dtype));
+    }
+    // Tuned knobs of the expression reductions on the interpreter live under
+    // route -2.
     s = resolve(cfg, lookup(nrm2 ? kNrm2 : kDot, -2, dtype, n, nrm2 ? 1 : 2), nrm2 ? kNrm2 : kDot, &c);
     if (s != SALT_OK) return s;
     L.result = result;
@@ -471,7 +524,52 @@ salt_status reduce_expr_impl(const uint32_t *px, int32_t lx, const uint32_t *py,
     return device_status(launch_reduce_expr(L, gx, nrm2 ? nullptr : &gy, dtype));
 }
 
+// Canonical numbering over the concatenation of two validated programs:
+// operands and scalars numbered by first appearance in a, then in b.
+void canon_pair(const uint32_t *a, int32_t la, const uint32_t *b, int32_t lb, uint32_t *ca, uint32_t *cb,
+                int32_t *op_map, int32_t *sc_map) {
+    int32_t opn[SALT_MAX_OPERANDS], scn[SALT_MAX_SCALARS];
+    for (auto &x : opn) x = -1;
+    for (auto &x : scn) x = -1;
+    int no = 0, ns = 0;
+    const auto one = [&](uint32_t t) -> uint32_t {
+        const uint32_t op = t & 0xffu, arg = t >> 8;
+        if (op == SALT_OP_LOAD) {
+            if (opn[arg] < 0) op_map[no] = (int32_t)arg, opn[arg] = no++;
+            return SALT_TOKEN(SALT_OP_LOAD, opn[arg]);
+        }
+        if (op == SALT_OP_SCALAR) {
+            if (scn[arg] < 0) sc_map[ns] = (int32_t)arg, scn[arg] = ns++;
+            return SALT_TOKEN(SALT_OP_SCALAR, scn[arg]);
+        }
+        return t;
+    };
+    for (int i = 0; i < la; ++i) ca[i] = one(a[i]);
+    for (int i = 0; i < lb; ++i) cb[i] = one(b[i]);
+}
+
 }  // namespace
+
+int route_pair(const uint32_t *px, int32_t lx, const uint32_t *py, int32_t ly, int32_t *op_map,
+               int32_t *sc_map) {
+    const auto &cat = rcatalogue();
+    for (int order = 0; order < (py ? 2 : 1); ++order) {
+        const uint32_t *a = order ? py : px, *b = order ? px : py;
+        const int32_t la = order ? ly : lx, lb = py ? (order ? lx : ly) : 0;
+        uint32_t ca[SALT_MAX_TOKENS], cb[SALT_MAX_TOKENS];
+        int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
+        canon_pair(a, la, b, lb, ca, cb, om, sm);
+        for (size_t id = 0; id < cat.size(); ++id) {
+            const RcatEntry &e = cat[id];
+            if (e.lp != la || e.lq != lb) continue;
+            if (std::memcmp(e.p, ca, sizeof(uint32_t) * la) || std::memcmp(e.q, cb, sizeof(uint32_t) * lb)) continue;
+            std::memcpy(op_map, om, sizeof om);
+            std::memcpy(sc_map, sm, sizeof sm);
+            return (int)id;
+        }
+    }
+    return -1;
+}
 
 salt_status tuned_config(int kind, int route, int dtype, int64_t n, salt_launch_config *out) {
     if (!out || !dtype_ok(dtype)) return SALT_ERR_ARG;
@@ -971,6 +1069,21 @@ salt_status salt_program_route(const uint32_t *prog, int32_t prog_len, int32_t n
     const salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
     if (s != SALT_OK) return fail(s, why);
     if (route) *route = route_of(p);
+    return SALT_OK;
+}
+
+salt_status salt_reduce_expr_route(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,
+                                   int32_t n_operands, int32_t n_scalars, int32_t *route) {
+    Program p;
+    std::string why;
+    salt_status s = compile_program(prog_x, len_x, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, "first program: " + why);
+    if (prog_y) {
+        s = compile_program(prog_y, len_y, n_operands, n_scalars, &p, &why);
+        if (s != SALT_OK) return fail(s, "second program: " + why);
+    }
+    int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
+    if (route) *route = route_pair(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm);
     return SALT_OK;
 }
 

@@ -94,4 +94,39 @@ enum Id {
 // Route of a program: a catalogue id, or kRouteGeneric for the interpreter.
 constexpr int kRouteGeneric = -1;
 
+// The empty second tree of a norm: nrm2(P) is the pair (P, NoTree).
+struct NoTree {
+    static constexpr int len = 0, n_loads = 0, n_scal = 0;
+    static constexpr void emit(uint32_t *, int &) {}
+};
+
+// Reductions of trees with their own ahead-of-time kernels (the lazy
+// evaluation of a tree inside a dot product or a norm, Sec. 2): dot(P, Q),
+// or nrm2(P) when Q is NoTree. Operands and scalars are numbered in order of
+// first appearance in P, then in Q; any other pair runs on the interpreter.
+namespace rcat {
+struct dot_sum_diff {  // dot(a + b, a - b)
+    using P = Add<Ld<0>, Ld<1>>;
+    using Q = Sub<Ld<0>, Ld<1>>;
+};
+struct nrm2_diff {  // nrm2(a - b): the norm of a difference
+    using P = Sub<Ld<0>, Ld<1>>;
+    using Q = NoTree;
+};
+struct nrm2_axpy {  // nrm2(alpha*a + b): the norm of an axpy result
+    using P = Add<Mul<Sc<0>, Ld<0>>, Ld<1>>;
+    using Q = NoTree;
+};
+}  // namespace rcat
+#define SALT_RCATALOGUE(X) X(dot_sum_diff) X(nrm2_diff) X(nrm2_axpy)
+
+namespace rcat {
+enum Id {
+#define SALT_RCAT_ID(name) id_##name,
+    SALT_RCATALOGUE(SALT_RCAT_ID)
+#undef SALT_RCAT_ID
+    count
+};
+}  // namespace rcat
+
 }  // namespace salt

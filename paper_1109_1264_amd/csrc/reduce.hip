@@ -34,4 +34,14 @@ hipError_t launch_reduce_expr(const ReduceExprLaunch &L, const Program &px, cons
     }
 }
 
+hipError_t launch_reduce_tree(const ReduceExprLaunch &L, int id, int dtype) {
+    switch (dtype) {
+        case SALT_F64: return launch_reduce_tree_f64(L, id);
+        case SALT_F32: return launch_reduce_tree_f32(L, id);
+        case SALT_BF16: return launch_reduce_tree_bf16(L, id);
+        case SALT_F16: return launch_reduce_tree_f16(L, id);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace salt

@@ -7,4 +7,5 @@ hipError_t launch_reduce_f64(const ReduceLaunch &L) { return launch_reduce_dt<SA
 hipError_t launch_reduce_expr_f64(const ReduceExprLaunch &L, const Program &px, const Program *py) {
     return launch_reduce_expr_dt<SALT_F64>(L, px, py);
 }
+hipError_t launch_reduce_tree_f64(const ReduceExprLaunch &L, int id) { return launch_reduce_tree_dt<SALT_F64>(L, id); }
 }  // namespace salt

@@ -15,6 +15,7 @@
 // on alignment nor on the launch shape.
 #pragma once
 
+#include "expr.hpp"
 #include "interp.hpp"
 #include "launch.hpp"
 #include "reduce_common.hpp"
@@ -230,6 +231,106 @@ __global__ __launch_bounds__(kBlock) void k_reduce_expr(RedExprArgs<DT> a, Inter
     }
 }
 
+// The same reductions for a pair (P, Q) of compile-time trees (or P alone
+// for nrm2): straight-line code per element instead of the interpreter.
+// Values, roundings, zeros past n and the accumulation order are those of
+// k_reduce_expr, so the bits are the same; a single tile stores its result
+// from here, as salt_dot does.
+template <int DT, int NL, int U, int NS>
+struct RChunkCtx {
+    using C = typename Tr<DT>::C;
+    const u32x4 (&raw)[NL][U];
+    const C (&s)[NS];
+    int u, p;
+    template <int K>
+    __device__ __forceinline__ C ld() const { return Tr<DT>::get(raw[K][u], p); }
+    template <int J>
+    __device__ __forceinline__ C sc() const { return s[J]; }
+};
+
+template <int DT>
+struct RedTreeArgs {
+    const void *ops[SALT_MAX_OPERANDS];  // canonical numbering of the pair
+    typename Tr<DT>::C sc[SALT_MAX_SCALARS];
+    double *ws;
+    int64_t n;
+    int32_t vec;
+    void *result;
+    int32_t final_store;  // n fits one tile: store the result from here
+};
+
+template <class P, class Q, int DT, int UR, bool NT>
+__global__ __launch_bounds__(kBlock) void k_reduce_tree(RedTreeArgs<DT> a) {
+    using C = typename Tr<DT>::C;
+    constexpr bool NRM = Q::len == 0;
+    constexpr int V = Tr<DT>::V;
+    constexpr int64_t T = tile_elems<DT>();
+    constexpr int NL = cmax(cmax(P::n_loads, Q::n_loads), 1);
+    constexpr int NS = cmax(cmax(P::n_scal, Q::n_scal), 1);
+    const int64_t n_tiles = (a.n + T - 1) / T;
+    const int64_t n_full = a.vec ? a.n / T : 0;
+    __shared__ double lds[kBlock / 64];
+    const void *op[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) op[k] = a.ops[k];
+    C s[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) s[j] = a.sc[j];
+    // the values salt_eval would store, multiplied in the accumulators
+    const auto add_chunk = [&](Acc<DT>(&acc)[V], const u32x4(&raw)[NL][UR], int u, int64_t first, bool check) {
+#pragma unroll
+        for (int p = 0; p < V; ++p) {
+            const RChunkCtx<DT, NL, UR, NS> g{raw, s, u, p};
+            C x = Tr<DT>::round(P::ev(g));
+            C y = x;
+            if constexpr (!NRM) y = Tr<DT>::round(Q::ev(g));
+            if (check && first + p >= a.n) x = y = (C)0;
+            acc[p].add(x, y);
+        }
+    };
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        Acc<DT> acc[V];
+        const int64_t c0 = t * ((int64_t)kBlock * kChunksPerLane) + threadIdx.x;
+        if (t < n_full) {
+#pragma unroll 1
+            for (int it0 = 0; it0 < kChunksPerLane; it0 += UR) {
+                u32x4 raw[NL][UR];
+#pragma unroll
+                for (int k = 0; k < P::n_loads || k < Q::n_loads; ++k)
+#pragma unroll
+                    for (int u = 0; u < UR; ++u) raw[k][u] = ld16<NT>((const u32x4 *)op[k] + c0 + (int64_t)(it0 + u) * kBlock);
+#pragma unroll
+                for (int u = 0; u < UR; ++u) add_chunk(acc, raw, u, 0, false);
+            }
+        } else {
+            // the short tile: its rows with elements only, element-wise loads
+            // with zeros past n, and the values past n set to zero
+            const int64_t m = a.n - t * T;
+            const int rows = m < T ? (int)((m + (int64_t)kBlock * V - 1) / ((int64_t)kBlock * V)) : kChunksPerLane;
+#pragma unroll 1
+            for (int it0 = 0; it0 < rows; it0 += UR) {
+                u32x4 raw[NL][UR];
+#pragma unroll
+                for (int k = 0; k < P::n_loads || k < Q::n_loads; ++k)
+#pragma unroll
+                    for (int u = 0; u < UR; ++u) {
+                        raw[k][u] = u32x4{0u, 0u, 0u, 0u};
+                        if (it0 + u < rows)
+                            raw[k][u] = load_chunk_guarded<DT, NT>(op[k], c0 + (int64_t)(it0 + u) * kBlock, a.n, a.vec);
+                    }
+#pragma unroll
+                for (int u = 0; u < UR; ++u)
+                    if (it0 + u < rows) add_chunk(acc, raw, u, (c0 + (int64_t)(it0 + u) * kBlock) * V, true);
+            }
+        }
+        const double v = block_sum<kBlock / 64>(lane_value<DT>(acc), lds);
+        if (threadIdx.x == 0) {
+            if (a.final_store) store_result<DT, NRM>(a.result, v);
+            else a.ws[t] = v;
+        }
+    }
+}
+
 template <int DT, bool NRM>
 __global__ __launch_bounds__(kFinalBlock) void k_reduce_pass2(const double *ws, int64_t n_tiles, void *result) {
     __shared__ double lds[kFinalBlock / 64];
@@ -370,6 +471,59 @@ static hipError_t launch_reduce_expr_dt(const ReduceExprLaunch &L, const Program
     return hipGetLastError();
 }
 
+template <class P, class Q, int DT, int UR, bool NT>
+static void launch_tree_k(dim3 gd, hipStream_t s, const RedTreeArgs<DT> &a) {
+    hipLaunchKernelGGL((k_reduce_tree<P, Q, DT, UR, NT>), gd, dim3(kBlock), 0, s, a);
+}
+
+template <class P, class Q, int DT>
+static hipError_t launch_reduce_tree_pq(const ReduceExprLaunch &L) {
+    constexpr bool NRM = Q::len == 0;
+    const int64_t T = tile_elems<DT>();
+    const int64_t n_tiles = (L.n + T - 1) / T;
+    if (n_tiles == 0) {
+        // an empty reduction: pass 2 over no partials stores zero
+        hipLaunchKernelGGL((k_reduce_pass2<DT, NRM>), dim3(1), dim3(kFinalBlock), 0, (hipStream_t)L.stream,
+                           (const double *)L.ws, (int64_t)0, L.result);
+        return hipGetLastError();
+    }
+    RedTreeArgs<DT> a;
+    for (int k = 0; k < SALT_MAX_OPERANDS; ++k) a.ops[k] = L.ops[k];
+    for (int j = 0; j < SALT_MAX_SCALARS; ++j) a.sc[j] = (typename Tr<DT>::C)L.sc[j];
+    a.ws = L.ws;
+    a.n = L.n;
+    a.vec = L.vec;
+    a.result = L.result;
+    a.final_store = n_tiles == 1 ? 1 : 0;
+    int64_t grid = L.blocks > 0 && L.blocks < n_tiles ? L.blocks : n_tiles;
+    if (grid > 0x7fffffff) grid = 0x7fffffff;
+    const dim3 gd((unsigned)grid);
+    hipStream_t s = (hipStream_t)L.stream;
+    const bool nt = L.nontemporal != 0;
+    switch (L.unroll) {
+        case 2: nt ? launch_tree_k<P, Q, DT, 2, true>(gd, s, a) : launch_tree_k<P, Q, DT, 2, false>(gd, s, a); break;
+        case 4: nt ? launch_tree_k<P, Q, DT, 4, true>(gd, s, a) : launch_tree_k<P, Q, DT, 4, false>(gd, s, a); break;
+        case 16: nt ? launch_tree_k<P, Q, DT, 16, true>(gd, s, a) : launch_tree_k<P, Q, DT, 16, false>(gd, s, a); break;
+        default: nt ? launch_tree_k<P, Q, DT, 8, true>(gd, s, a) : launch_tree_k<P, Q, DT, 8, false>(gd, s, a); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_tiles == 1) return e;
+    hipLaunchKernelGGL((k_reduce_pass2<DT, NRM>), dim3(1), dim3(kFinalBlock), 0, s, (const double *)L.ws, n_tiles,
+                       L.result);
+    return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t launch_reduce_tree_dt(const ReduceExprLaunch &L, int id) {
+    switch (id) {
+#define SALT_RCAT_CASE(name) \
+    case rcat::id_##name: return launch_reduce_tree_pq<rcat::name::P, rcat::name::Q, DT>(L);
+        SALT_RCATALOGUE(SALT_RCAT_CASE)
+#undef SALT_RCAT_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_reduce_f64(const ReduceLaunch &L);
 hipError_t launch_reduce_f32(const ReduceLaunch &L);
 hipError_t launch_reduce_bf16(const ReduceLaunch &L);
@@ -378,5 +532,9 @@ hipError_t launch_reduce_expr_f64(const ReduceExprLaunch &L, const Program &px, 
 hipError_t launch_reduce_expr_f32(const ReduceExprLaunch &L, const Program &px, const Program *py);
 hipError_t launch_reduce_expr_bf16(const ReduceExprLaunch &L, const Program &px, const Program *py);
 hipError_t launch_reduce_expr_f16(const ReduceExprLaunch &L, const Program &px, const Program *py);
+hipError_t launch_reduce_tree_f64(const ReduceExprLaunch &L, int id);
+hipError_t launch_reduce_tree_f32(const ReduceExprLaunch &L, int id);
+hipError_t launch_reduce_tree_bf16(const ReduceExprLaunch &L, int id);
+hipError_t launch_reduce_tree_f16(const ReduceExprLaunch &L, int id);
 
 }  // namespace salt

@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         "salt_catalogue_count": ([], I32),
         "salt_catalogue_program": ([I32, U32P, I32, ctypes.POINTER(ctypes.c_char_p)], I32),
         "salt_program_route": ([U32P, I32, I32, I32, ctypes.POINTER(I32)], I32),
+        "salt_reduce_expr_route": ([U32P, I32, U32P, I32, I32, I32, ctypes.POINTER(I32)], I32),
         "salt_program_check": ([U32P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)], I32),
         "salt_status_string": ([I32], ctypes.c_char_p),
         "salt_last_error": ([], ctypes.c_char_p),
@@ -498,6 +499,17 @@ def salt_program_route(prog: Sequence[int], n_operands: int, n_scalars: int) -> 
     parr, plen = _prog(prog)
     r = ctypes.c_int32()
     check(lib().salt_program_route(parr, plen, n_operands, n_scalars, ctypes.byref(r)))
+    return r.value
+
+
+def salt_reduce_expr_route(prog_x: Sequence[int], prog_y: Sequence[int] | None, n_operands: int,
+                           n_scalars: int) -> int:
+    """Reduction-pair catalogue index the expression reduction runs, or -1
+    (the interpreter)."""
+    px, lx = _prog(prog_x)
+    py, ly = _prog(prog_y) if prog_y is not None else (None, 0)
+    r = ctypes.c_int32()
+    check(lib().salt_reduce_expr_route(px, lx, py, ly, n_operands, n_scalars, ctypes.byref(r)))
     return r.value
 
 

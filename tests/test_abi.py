@@ -304,3 +304,28 @@ def test_stream_reference_argument_errors(L):
     odd = (ctypes.c_void_p * 2)((1 << 40) + 8, 1 << 40)
     assert L.salt_stream_reference(2, 1, odd, out, 64, None) == S.ERR_ARG       # misaligned input
     assert L.salt_stream_reference(2, 1, fake, out, 0, None) == S.OK           # nothing to do
+
+
+def test_reduce_expr_route_matches_the_pair_catalogue():
+    """Expression reductions that match a catalogue pair under canonical
+    numbering (operands and scalars by first use, P then Q; a dot's programs
+    in either order) route to its ahead-of-time kernel; anything else to the
+    interpreter (-1). Host only."""
+    L0, L1, L2, L3 = T(S.LOAD, 0), T(S.LOAD, 1), T(S.LOAD, 2), T(S.LOAD, 3)
+    ADD, SUB, MUL = T(S.ADD), T(S.SUB), T(S.MUL)
+    r = S.salt_reduce_expr_route
+    assert r([L0, L1, ADD], [L0, L1, SUB], 2, 0) == 0            # dot(a + b, a - b)
+    assert r([L2, L3, ADD], [L2, L3, SUB], 4, 0) == 0            # other operand numbers
+    assert r([L0, L1, SUB], [L0, L1, ADD], 2, 0) == 0            # programs exchanged
+    assert r([L1, L0, ADD], [L0, L1, SUB], 2, 0) == -1           # b + a: not the same tokens
+    assert r([L0, L1, ADD], [L1, L0, SUB], 2, 0) == -1           # a + b with b - a
+    assert r([L0, L1, SUB], None, 2, 0) == 1                     # nrm2(a - b)
+    assert r([L1, L0, SUB], None, 2, 0) == 1                     # nrm2(b - a): renumbered
+    assert r([L0, L1, ADD], None, 2, 0) == -1
+    assert r([L0, L1, SUB], [L0, L1, SUB], 2, 0) == -1           # a dot, not a norm
+    assert r([T(S.SCALAR, 0), L0, MUL, L1, ADD], None, 2, 1) == 2   # nrm2(alpha*a + b)
+    assert r([T(S.SCALAR, 2), L3, MUL, L0, ADD], None, 4, 3) == 2   # other numbers
+    assert r([L0, T(S.SCALAR, 0), MUL, L1, ADD], None, 2, 1) == -1  # a*alpha: other tokens
+    assert r([T(S.SCALAR, 0), L0, MUL, L0, ADD], None, 2, 1) == -1  # one operand twice
+    with pytest.raises(S.SaltError):
+        r([L0, L1, ADD], [L0, L2, SUB], 2, 0)                     # operand out of range

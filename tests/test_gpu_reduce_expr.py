@@ -144,3 +144,82 @@ def test_interpreter_unroll_shapes(dtype):
             S.salt_eval(prog, dev, [], out, config=(unroll, 1, blocks))
             torch.cuda.synchronize()
             assert np.array_equal(to_host_bits(out, dtype), np.ascontiguousarray(want).view(to_host_bits(out, dtype).dtype)), (unroll, blocks)
+
+
+# The reduction pairs with ahead-of-time kernels, each with an equivalent
+# program pair that the catalogue does not match (an addition with its
+# operands exchanged gives the same bits in IEEE arithmetic), so it runs on
+# the interpreter.
+L0, L1, L2, L3, S0 = T(S.LOAD, 0), T(S.LOAD, 1), T(S.LOAD, 2), T(S.LOAD, 3), T(S.SCALAR, 0)
+PAIRS = {
+    "dot_sum_diff": (([L0, L1, T(S.ADD)], [L0, L1, T(S.SUB)]), ([L1, L0, T(S.ADD)], [L0, L1, T(S.SUB)])),
+    "nrm2_diff": (([L0, L1, T(S.SUB)], None), ([T(S.SCALAR, 1), L0, L1, T(S.SUB)] + [T(S.MUL)], None)),
+    "nrm2_axpy": (([S0, L0, T(S.MUL), L1, T(S.ADD)], None), ([L1, S0, L0, T(S.MUL), T(S.ADD)], None)),
+}
+
+
+def run_pair(px, py, dev, sc, n, cfg=None):
+    if py is None:
+        return S.salt_nrm2_expr(px, dev, sc, n=n, config=cfg)
+    return S.salt_dot_expr(px, py, dev, sc, n=n, config=cfg)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", list(PAIRS))
+def test_ahead_of_time_pairs(dtype, name):
+    """Each catalogue pair routes to its ahead-of-time kernel and has the bits
+    of (i) evaluating its trees with salt_eval and reducing the vectors, and
+    (ii) the interpreter running an equivalent pair; and it is within the
+    tolerance of the oracle's Dot2 of the oracle-evaluated vectors. Lengths
+    cover the empty, single-tile, ragged and multi-tile cases, aligned and
+    not."""
+    import torch
+
+    (px, py), (qx, qy) = PAIRS[name]
+    assert S.salt_reduce_expr_route(px, py, 2, 2) == list(PAIRS).index(name)
+    assert S.salt_reduce_expr_route(qx, qy, 2, 2) == -1
+    # the interpreter variant of nrm2_diff multiplies by scalar 1 = 1.0 (exact)
+    sc = [1.375, 1.0]
+    Tt = S.salt_reduce_tile_elems(CODE[dtype])
+    for n in (0, 1, 100, Tt - 3, Tt, Tt + 1, 3 * Tt + 11, 300001):
+        for off in (0, 1):
+            host = workloads.uniform(n, dtype, 70 + n % 89 + off, 2)
+            dev = [to_dev(h, dtype, offset=off) for h in host]
+            r = run_pair(px, py, dev, sc, n)
+            r_int = run_pair(qx, qy, dev, sc, n)
+            ex, ey = (composed([px, py], dev, sc, dtype, n) if py is not None
+                      else composed([px], dev, sc, dtype, n) + [None])
+            r_comp = S.salt_dot(ex, ey, n=n) if py is not None else S.salt_nrm2(ex, n=n)
+            torch.cuda.synchronize()
+            assert r.item() == r_comp.item(), (name, dtype, n, off, r.item(), r_comp.item())
+            assert r.item() == r_int.item(), (name, dtype, n, off, r.item(), r_int.item())
+            vx = oracle.widen(oracle.eval_program(px, host, sc, dtype, n=n), dtype)
+            vy = vx if py is None else oracle.widen(oracle.eval_program(py, host, sc, dtype, n=n), dtype)
+            ref, abs_sum = oracle.dot2(vx, vy)
+            if py is None:
+                assert abs(r.item() - np.sqrt(ref)) <= oracle.TOL[dtype] * np.sqrt(ref) + 1e-300
+            else:
+                assert abs(r.item() - ref) <= oracle.TOL[dtype] * abs_sum + 1e-300
+
+
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_ahead_of_time_pairs_launch_shapes_and_numbering(dtype):
+    """Launch knobs do not change the bits of an ahead-of-time pair, and the
+    pair is found under any operand numbering (operands 3 and 1 of four)."""
+    import torch
+
+    n = 5 * S.salt_reduce_tile_elems(CODE[dtype]) + 333
+    host = workloads.uniform(n, dtype, 14, 4)
+    dev = [to_dev(h, dtype) for h in host]
+    px, py = [L3, L1, T(S.ADD)], [L3, L1, T(S.SUB)]
+    assert S.salt_reduce_expr_route(px, py, 4, 0) == 0
+    assert S.salt_reduce_expr_route(py, px, 4, 0) == 0          # programs exchanged
+    ref = S.salt_dot_expr(px, py, dev, []).item()
+    assert S.salt_dot_expr(py, px, dev, []).item() == ref
+    ex, ey = composed([px, py], dev, [], dtype, n)
+    assert S.salt_dot(ex, ey).item() == ref
+    for unroll in (2, 4, 8, 16):
+        for nt in (0, 1):
+            for blocks in (0, 7, 256):
+                cfg = (unroll, nt, blocks)
+                assert S.salt_dot_expr(px, py, dev, [], config=cfg).item() == ref, cfg
