@@ -8,7 +8,8 @@ a tuning table that libsalt loads at start-up (``salt_tuning.txt`` beside the
 library, or ``$SALT_TUNE_FILE``). None of the knobs changes a result bit, so
 the table only moves time.
 
-    python -m paper_1109_1264_amd.autotune --out paper_1109_1264_amd/salt_tuning.txt
+    python -m paper_1109_1264_amd.autotune --rotate --rotate-from-mib 128 \
+        --out paper_1109_1264_amd/salt_tuning.txt
 """
 from __future__ import annotations
 
@@ -76,12 +77,19 @@ T_ = S.token
 INTERP_PROG = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD), T_(S.LOAD, 2), T_(S.MUL)]   # (a + b) * c
 EXPR_P = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD)]                                  # a + b
 EXPR_Q = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.SUB)]                                  # a - b
+# The reduction pairs with ahead-of-time kernels (route -16 - index), in the
+# library's catalogue order: (P, Q or None for nrm2).
+PAIRS = [(EXPR_P, EXPR_Q),                                                         # dot(a + b, a - b)
+         (EXPR_Q, None),                                                           # nrm2(a - b)
+         ([T_(S.SCALAR, 0), T_(S.LOAD, 0), T_(S.MUL), T_(S.LOAD, 1), T_(S.ADD)], None)]  # nrm2(alpha*a + b)
+PAIR_ROUTE0 = -16
 
 
 class Workload:
     """Device buffers for one (kind, tree, dtype) at the largest size swept."""
 
-    def __init__(self, kind: str, tree: str | None, dtype: int, n_max: int, rotate: bool = False):
+    def __init__(self, kind: str, tree: str | None, dtype: int, n_max: int, rotate: bool = False,
+                 rotate_from: int = 4 << 20):
         import torch
 
         if rotate:
@@ -89,6 +97,7 @@ class Workload:
             # slices to rotate through (see sets())
             n_max = max(n_max, (1 << 30) // S.ELEM_BYTES[dtype])
         self.kind, self.dtype, self.n_max, self.rotate = kind, dtype, n_max, rotate
+        self.rotate_from = rotate_from
         td = _torch_dtype(dtype)
         cat = dict(S.salt_catalogue())
         self.route = -1
@@ -98,6 +107,13 @@ class Workload:
             self.sc = []
             self.out = torch.empty(n_max, dtype=td, device="cuda")
             self.arrays = 4
+        elif kind.startswith("pair"):
+            self.pair = int(kind[4:])
+            self.route = PAIR_ROUTE0 - self.pair
+            self.ops = [torch.rand(n_max, device="cuda").to(td) for _ in range(2)]
+            self.ws = S.workspace(n_max, dtype)
+            self.res = torch.empty(1, dtype=torch.float64 if dtype == S.F64 else torch.float32, device="cuda")
+            self.arrays = 2
         elif kind in ("dotx", "nrm2x"):
             self.route = -2
             self.ops = [torch.rand(n_max, device="cuda").to(td) for _ in range(2)]
@@ -126,9 +142,10 @@ class Workload:
         buffers, so working sets below the 256 MiB last-level cache are timed
         cache-resident, as in iterative use of the same vectors. With
         rotation: enough slices for about 1 GiB (at most 64), so a working
-        set between 4 MiB and 1 GiB streams from HBM."""
+        set between `rotate_from` (4 MiB by default) and 1 GiB streams from
+        HBM."""
         ws = self.arrays * S.ELEM_BYTES[self.dtype] * n
-        if not self.rotate or ws >= (1 << 30) or ws < (4 << 20):
+        if not self.rotate or ws >= (1 << 30) or ws < max(4 << 20, self.rotate_from):
             return 1
         return int(min(64, self.n_max // n, -(-(1 << 30) // ws)))
 
@@ -145,6 +162,13 @@ class Workload:
                 state["k"] += 1
             return run
 
+        if self.kind.startswith("pair"):
+            px, py = PAIRS[self.pair]
+            if py is None:
+                return step(lambda cfg: S.salt_nrm2_expr(px, [sl(o) for o in self.ops], [1.25], n=n,
+                                                         result=self.res, ws=self.ws, config=cfg))
+            return step(lambda cfg: S.salt_dot_expr(px, py, [sl(o) for o in self.ops], [1.25], n=n,
+                                                    result=self.res, ws=self.ws, config=cfg))
         if self.kind == "dotx":
             return step(lambda cfg: S.salt_dot_expr(EXPR_P, EXPR_Q, [sl(o) for o in self.ops], [], n=n,
                                                     result=self.res, ws=self.ws, config=cfg))
@@ -160,12 +184,12 @@ class Workload:
 
 
 def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbose: bool = False,
-         rotate: bool = False):
+         rotate: bool = False, rotate_from: int = 4 << 20):
     """Rows (kind, route, dtype, log2n, unroll, nt, blocks, best_ms, GBps)."""
     import torch
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    w = Workload(kind, tree, dtype, 1 << max(log2ns), rotate=rotate)
+    w = Workload(kind, tree, dtype, 1 << max(log2ns), rotate=rotate, rotate_from=rotate_from)
     rows = []
     for l in log2ns:
         n = 1 << l
@@ -179,6 +203,8 @@ def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbos
         t, (u, nt, b) = best
         gbps = w.arrays * n * S.ELEM_BYTES[dtype] / (t * 1e-3) / 1e9
         table_kind = {"interp": "eval", "dotx": "dot", "nrm2x": "nrm2"}.get(kind, kind)
+        if kind.startswith("pair"):
+            table_kind = "nrm2" if PAIRS[w.pair][1] is None else "dot"
         rows.append((table_kind, w.route, dtype, l, u, nt, b, t, gbps))
         if verbose:
             print("tuned %s %s %s 2^%d: unroll=%d nt=%d blocks=%d %.4f ms %.0f GB/s"
@@ -274,31 +300,39 @@ def main(argv=None) -> int:
     ap.add_argument("--dtypes", default="f64,f32,bf16,f16")
     ap.add_argument("--log2n", default="10-28")
     ap.add_argument("--reps", type=int, default=10)
-    ap.add_argument("--step", type=int, default=2, help="tune every step-th log2 size")
-    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,dotx,nrm2x,batch")
+    ap.add_argument("--step", type=int, default=1, help="tune every step-th log2 size")
+    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,dotx,nrm2x,pairs,batch")
     ap.add_argument("--json", default=None, help="also write all rows as JSON here")
     ap.add_argument("--rotate", action="store_true",
                     help="time working sets of 4 MiB .. 1 GiB streaming from HBM (buffer slices cycled) "
                          "instead of cache-resident")
+    ap.add_argument("--rotate-from-mib", type=int, default=4,
+                    help="with --rotate, only working sets of at least this many MiB are streamed; smaller "
+                         "ones are timed cache-resident")
     args = ap.parse_args(argv)
     lo, hi = (int(v) for v in args.log2n.split("-"))
     sizes = list(range(lo, hi + 1, args.step))
     if sizes[-1] != hi:
         sizes.append(hi)
     kinds = args.kinds.split(",")
+    rf = args.rotate_from_mib << 20
     t0 = time.time()
     rows = []
     for dname in args.dtypes.split(","):
         d = DT_NAMES[dname]
         for kind in ("dot", "nrm2"):
             if kind in kinds:
-                rows += tune(kind, None, d, sizes, args.reps, verbose=True, rotate=args.rotate)
+                rows += tune(kind, None, d, sizes, args.reps, verbose=True, rotate=args.rotate, rotate_from=rf)
         if "eval" in kinds:
             for tree in args.trees.split(","):
-                rows += tune("eval", tree, d, sizes, args.reps, verbose=True, rotate=args.rotate)
+                rows += tune("eval", tree, d, sizes, args.reps, verbose=True, rotate=args.rotate, rotate_from=rf)
         for kind in ("interp", "dotx", "nrm2x"):
             if kind in kinds:
-                rows += tune(kind, None, d, sizes, args.reps, verbose=True, rotate=args.rotate)
+                rows += tune(kind, None, d, sizes, args.reps, verbose=True, rotate=args.rotate, rotate_from=rf)
+        if "pairs" in kinds:
+            for i in range(len(PAIRS)):
+                rows += tune("pair%d" % i, None, d, sizes, args.reps, verbose=True, rotate=args.rotate,
+                             rotate_from=rf)
     if "batch" in kinds:
         from . import workloads
 

@@ -16,9 +16,9 @@ def test_candidate_grid():
     assert {u for u, _, _ in A.candidates("batch", 1 << 20, S.F32, 256)} == {2, 4, 8}
 
 
-def workload(arrays, dtype, n_max, rotate):
+def workload(arrays, dtype, n_max, rotate, rotate_from=4 << 20):
     w = A.Workload.__new__(A.Workload)   # no device buffers: only the policy
-    w.arrays, w.dtype, w.n_max, w.rotate = arrays, dtype, n_max, rotate
+    w.arrays, w.dtype, w.n_max, w.rotate, w.rotate_from = arrays, dtype, n_max, rotate, rotate_from
     return w
 
 
@@ -38,11 +38,29 @@ def test_rotation_policy():
         assert w.sets(n) * n <= w.n_max
 
 
+def test_rotation_threshold():
+    """Streaming only from the threshold up: below it the working set is
+    timed cache-resident."""
+    w = workload(2, S.F32, 1 << 28, True, rotate_from=128 << 20)
+    assert w.sets(1 << 23) == 1            # 64 MiB: resident
+    assert w.sets(1 << 24) == 8            # 128 MiB: 1 GiB worth of slices
+    assert w.sets(1 << 26) == 2            # 512 MiB
+    assert w.sets(1 << 27) == 1            # 1 GiB
+
+
+def test_reduction_pairs_follow_the_library_catalogue():
+    """The tuner's pair list is the library's reduction-pair catalogue, in
+    order (each routes to its own index)."""
+    for i, (px, py) in enumerate(A.PAIRS):
+        assert S.salt_reduce_expr_route(px, py, 2, 1) == i
+
+
 def test_written_table_reads_back(tmp_path):
     rows = [("eval", 2, S.F64, 20, 2, 1, 512, 0.0043, 7892.0),
             ("dot", -1, S.F32, 26, 16, 0, 1024, 0.085, 6300.0),
             ("nrm2", -2, S.BF16, 24, 4, 1, 0, 0.019, 3500.0),
-            ("batch", 5, S.F32, 25, 8, 1, 4096, 0.153, 5300.0)]
+            ("batch", 5, S.F32, 25, 8, 1, 4096, 0.153, 5300.0),
+            ("dot", A.PAIR_ROUTE0, S.BF16, 28, 8, 1, 256, 0.171, 6266.0)]
     p = tmp_path / "t.txt"
     A.write_table(rows, str(p))
     S.salt_tuning_load(str(p))
@@ -51,5 +69,6 @@ def test_written_table_reads_back(tmp_path):
         assert S.salt_tuning_lookup(1, -1, S.F32, 1 << 26) == (16, 0, 1024)
         assert S.salt_tuning_lookup(2, -2, S.BF16, 1 << 24) == (4, 1, 0)
         assert S.salt_tuning_lookup(3, 5, S.F32, 50645917) == (8, 1, 4096)
+        assert S.salt_tuning_lookup(1, A.PAIR_ROUTE0, S.BF16, 1 << 28) == (8, 1, 256)
     finally:
         S.salt_tuning_load(None)
