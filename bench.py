@@ -540,6 +540,49 @@ def section_fusion(args):
     torch.cuda.empty_cache()
     out["fig1_n2p20"] = fig1_small()
     out["expression_reductions"] = expression_reductions(args)
+    out["compiled_trees"] = compiled_trees()
+    return out
+
+
+def compiled_trees():
+    """A tree outside the catalogue, (a + b) * c, on the interpreter against
+    its run-time compiled kernel, by element type and size (device time per
+    launch of back-to-back launches, buffers reused), with identical bits."""
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    T = salt.token
+    prog = [T(salt.LOAD, 0), T(salt.LOAD, 1), T(salt.ADD), T(salt.LOAD, 2), T(salt.MUL)]
+    out = {"tree": "(a + b) * c", "bytes": "4 s bytes per element (3 reads, 1 write)"}
+    log("bench: compiled trees")
+    t0 = time.perf_counter()
+    for dt in ("f64", "f32", "bf16"):
+        salt.salt_jit_compile(prog, 3, 0, {"f64": salt.F64, "f32": salt.F32, "bf16": salt.BF16}[dt])
+    out["compile_seconds_three_types"] = round(time.perf_counter() - t0, 3)
+    for dt in ("f64", "f32", "bf16"):
+        es = {"f64": 8, "f32": 4, "bf16": 2}[dt]
+        rows = []
+        for l in (20, 22, 24, 26, 28):
+            n = 1 << l
+            a, b, c = workloads.uniform_device(n, dt, workloads.sweep_seed(n) + 5, 3)
+            d1 = torch.empty(n, dtype=a.dtype, device="cuda")
+            d2 = torch.empty(n, dtype=a.dtype, device="cuda")
+            reps = 20 if l <= 24 else 4
+            salt.salt_jit_set_mode(salt.JIT_OFF)
+            t_int = graph_ms(lambda: salt.salt_eval(prog, [a, b, c], [], d1), reps)
+            salt.salt_jit_set_mode(salt.JIT_EXPLICIT)
+            t_jit = graph_ms(lambda: salt.salt_eval(prog, [a, b, c], [], d2), reps)
+            salt.salt_jit_set_mode(salt.JIT_AUTO)
+            torch.cuda.synchronize()
+            same = bool(torch.equal(d1.view(torch.uint8), d2.view(torch.uint8)))
+            gb = lambda t: round(4 * es * n / (t * 1e-3) / 1e9, 1)
+            rows.append([l, round(t_int, 5), gb(t_int), round(t_jit, 5), gb(t_jit), same])
+            del a, b, c, d1, d2
+            torch.cuda.empty_cache()
+        out[dt] = {"columns": ["log2n", "interpreter_ms", "interpreter_GBps", "compiled_ms", "compiled_GBps",
+                               "same_bits"], "rows": rows}
     return out
 
 

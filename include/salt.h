@@ -421,6 +421,43 @@ typedef struct {
 salt_status salt_serve_trace(const salt_server_config *cfg, const salt_request *requests,
                              int32_t count, salt_request_result *results);
 
+/* ---- trees outside the catalogue: run-time compilation --------------------
+ * salt_eval runs a catalogue tree on its ahead-of-time kernel. Any other
+ * tree runs on a kernel compiled for it at run time (hipRTC, gfx950, with
+ * the library's own build rules: no contraction, no packed binary32
+ * instructions) once that kernel is ready, and on the interpreter until
+ * then; both give the same bits. Compiled kernels are cached per (tree in
+ * canonical numbering, element type) for the life of the process and
+ * loaded on a device at their first launch there (the runtime allocates
+ * their code memory then; a launch on a stream being captured into a graph
+ * does not load one and runs interpreted instead).
+ * Modes: SALT_JIT_OFF (always the interpreter); SALT_JIT_EXPLICIT (only
+ * trees passed to salt_jit_compile); SALT_JIT_AUTO (the default: a tree
+ * runs interpreted at its first call of at least 65536 elements, and its
+ * second such call compiles it on the calling thread, a one-time delay of
+ * the order of a second, then runs it compiled, as do later calls). */
+enum { SALT_JIT_OFF = 0, SALT_JIT_EXPLICIT = 1, SALT_JIT_AUTO = 2 };
+#define SALT_ROUTE_COMPILED (-3)
+salt_status salt_jit_set_mode(int32_t mode);
+
+/* Compile the tree of `prog` for `dtype` now and cache it (blocking; needs
+ * no GPU). SALT_OK also for a catalogue tree (nothing to do);
+ * SALT_ERR_UNSUPPORTED with the compiler's log in salt_last_error() if
+ * compilation fails. The program is validated as for salt_eval. */
+salt_status salt_jit_compile(const uint32_t *prog, int32_t prog_len,
+                             int32_t n_operands, int32_t n_scalars, salt_dtype dtype);
+
+/* The cached code object (gfx950 ELF) of a compiled tree: *size gets its
+ * size (0 if not compiled) and, when cap >= *size, buf a copy. */
+salt_status salt_jit_code(const uint32_t *prog, int32_t prog_len, int32_t n_operands,
+                          int32_t n_scalars, salt_dtype dtype, void *buf, size_t cap, size_t *size);
+
+/* Where salt_eval would run this program now: its catalogue index (>= 0),
+ * SALT_ROUTE_COMPILED when its run-time compiled kernel is ready, or -1
+ * (the interpreter). No GPU work. */
+salt_status salt_eval_route(const uint32_t *prog, int32_t prog_len, int32_t n_operands,
+                            int32_t n_scalars, salt_dtype dtype, int32_t *route);
+
 /* Which kernel salt_dot_expr (prog_y non-NULL) or salt_nrm2_expr (prog_y
  * NULL) runs for these programs, without touching the GPU: *route is the
  * index of the pair in the library's catalogue of reduction pairs with

@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libsalt.so")
 
 HIP_SOURCES = ["batch_f64.hip", "batch_f32.hip", "batch_bf16.hip", "batch_f16.hip",
                "reduce_f64.hip", "reduce_f32.hip", "reduce_bf16.hip", "reduce_f16.hip",
-               "eval.hip", "reduce.hip", "batch.hip", "blas1.hip", "server.hip", "stream_ref.hip", "api.hip"]
+               "eval.hip", "reduce.hip", "batch.hip", "blas1.hip", "server.hip", "stream_ref.hip", "jit.hip", "api.hip"]
 CXX_SOURCES = ["program.cpp"]
 ARCH = "gfx950"
 
@@ -68,7 +68,7 @@ def build(verbose: bool = False) -> str:
                 sys.stderr.write(p.stderr)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp,
-          *[o for _, o in jobs], "-ldl"])
+          *[o for _, o in jobs], "-ldl", "-lhiprtc"])
     os.replace(tmp, LIB)
     return LIB
 

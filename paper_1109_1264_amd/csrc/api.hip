@@ -22,6 +22,7 @@
 #include "batch.hpp"
 #include "blas1.hpp"
 #include "expr.hpp"
+#include "jit.hpp"
 #include "launch.hpp"
 #include "program.hpp"
 #include "salt.h"
@@ -277,6 +278,11 @@ salt_status eval_impl(const uint32_t *prog, int32_t prog_len, const void *const 
         if (!fn) return fail(SALT_ERR_UNSUPPORTED, "no kernel for this tree and dtype");
         return device_status(fn(L));
     }
+    // a tree outside the catalogue: its run-time compiled kernel when it is
+    // ready, else the interpreter (same bits either way)
+    bool ran = false;
+    const hipError_t je = jit_try_launch(L, p, dtype, &ran);
+    if (ran || je != hipSuccess) return device_status(je);
     return device_status(launch_interp(L, p, dtype));
 }
 
@@ -1084,6 +1090,52 @@ salt_status salt_reduce_expr_route(const uint32_t *prog_x, int32_t len_x, const 
     }
     int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
     if (route) *route = route_pair(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm);
+    return SALT_OK;
+}
+
+salt_status salt_jit_set_mode(int32_t mode) {
+    if (mode < kJitOff || mode > kJitAuto) return fail(SALT_ERR_ARG, "mode outside 0..2");
+    jit_set_mode(mode);
+    return SALT_OK;
+}
+
+salt_status salt_jit_compile(const uint32_t *prog, int32_t prog_len, int32_t n_operands, int32_t n_scalars,
+                             salt_dtype dtype) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    Program p;
+    std::string why;
+    salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, why);
+    if (route_of(p) != kRouteGeneric) return SALT_OK;  // a catalogue tree is compiled already
+    s = jit_compile(p, dtype, &why);
+    if (s != SALT_OK) return fail(s, why);
+    return SALT_OK;
+}
+
+salt_status salt_jit_code(const uint32_t *prog, int32_t prog_len, int32_t n_operands, int32_t n_scalars,
+                          salt_dtype dtype, void *buf, size_t cap, size_t *size) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    if (!size) return fail(SALT_ERR_ARG, "size pointer is NULL");
+    Program p;
+    std::string why;
+    const salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, why);
+    const std::vector<char> code = jit_code(p, dtype);
+    *size = code.size();
+    if (buf && cap >= code.size() && !code.empty()) std::memcpy(buf, code.data(), code.size());
+    return SALT_OK;
+}
+
+salt_status salt_eval_route(const uint32_t *prog, int32_t prog_len, int32_t n_operands, int32_t n_scalars,
+                            salt_dtype dtype, int32_t *route) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    Program p;
+    std::string why;
+    const salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, why);
+    int r = route_of(p);
+    if (r == kRouteGeneric && jit_mode() != kJitOff && jit_ready(p, dtype)) r = SALT_ROUTE_COMPILED;
+    if (route) *route = r;
     return SALT_OK;
 }
 

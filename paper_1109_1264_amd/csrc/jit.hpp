@@ -1,0 +1,57 @@
+// jit.hpp -- trees outside the catalogue compiled at run time (hipRTC).
+//
+// The paper builds every expression tree at compile time (Sec. 2); a tree
+// that only arrives at run time would otherwise run on the interpreter. Here
+// its canonical postfix form is turned into HIP source for the same loop as
+// the catalogue kernels (load bursts, the tree as straight-line code, store
+// bursts, per-element tail), compiled for gfx950 with hipRTC (contraction
+// off, packed binary32 instructions off, as the library itself is built),
+// cached per (tree, element type), loaded per device on first use and
+// launched instead of the interpreter. Same operations in the same order:
+// the results are bit-identical to the interpreter's and the oracle's.
+//
+// Compiling takes a fraction of a second, so in the automatic mode a tree
+// runs on the interpreter at its first call of at least kJitAutoMinElems
+// elements and is compiled (on the calling thread) at its second, which then
+// runs the compiled kernel, as do all later calls: a tree used once costs
+// nothing, a tree used repeatedly pays one compile. The explicit mode
+// compiles only what the caller asks for (salt_jit_compile).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "program.hpp"
+
+namespace salt {
+
+enum JitMode { kJitOff = 0, kJitExplicit = 1, kJitAuto = 2 };
+constexpr int64_t kJitAutoMinElems = (int64_t)1 << 16;
+
+// HIP source of the kernels for canonical program p in element type dtype.
+std::string jit_source(const Program &p, int dtype);
+
+// Launch p's compiled kernel if it is compiled (loading it on the current
+// device first unless the stream is being captured); *ran tells whether it
+// did. In the automatic mode a tree's second large call compiles it first.
+// L holds canonical operands and scalars, as for the catalogue kernels.
+hipError_t jit_try_launch(const EvalLaunch &L, const Program &p, int dtype, bool *ran);
+
+// Compile p for dtype now (blocking; no GPU needed). SALT_OK when the code
+// object is in the cache, SALT_ERR_UNSUPPORTED with hipRTC's log otherwise.
+salt_status jit_compile(const Program &p, int dtype, std::string *err);
+
+// Copy of the compiled code object (empty if not compiled).
+std::vector<char> jit_code(const Program &p, int dtype);
+
+// 1: compiled (ready to load and launch), 0: not (yet) compiled.
+int jit_ready(const Program &p, int dtype);
+
+void jit_set_mode(int mode);
+int jit_mode();
+
+}  // namespace salt

@@ -100,6 +100,10 @@ def lib() -> ctypes.CDLL:
         "salt_catalogue_program": ([I32, U32P, I32, ctypes.POINTER(ctypes.c_char_p)], I32),
         "salt_program_route": ([U32P, I32, I32, I32, ctypes.POINTER(I32)], I32),
         "salt_reduce_expr_route": ([U32P, I32, U32P, I32, I32, I32, ctypes.POINTER(I32)], I32),
+        "salt_jit_set_mode": ([I32], I32),
+        "salt_jit_compile": ([U32P, I32, I32, I32, I32], I32),
+        "salt_jit_code": ([U32P, I32, I32, I32, I32, P, SZ, ctypes.POINTER(SZ)], I32),
+        "salt_eval_route": ([U32P, I32, I32, I32, I32, ctypes.POINTER(I32)], I32),
         "salt_program_check": ([U32P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)], I32),
         "salt_status_string": ([I32], ctypes.c_char_p),
         "salt_last_error": ([], ctypes.c_char_p),
@@ -510,6 +514,38 @@ def salt_reduce_expr_route(prog_x: Sequence[int], prog_y: Sequence[int] | None, 
     py, ly = _prog(prog_y) if prog_y is not None else (None, 0)
     r = ctypes.c_int32()
     check(lib().salt_reduce_expr_route(px, lx, py, ly, n_operands, n_scalars, ctypes.byref(r)))
+    return r.value
+
+
+JIT_OFF, JIT_EXPLICIT, JIT_AUTO = 0, 1, 2
+ROUTE_COMPILED = -3
+
+
+def salt_jit_set_mode(mode: int) -> None:
+    check(lib().salt_jit_set_mode(mode))
+
+
+def salt_jit_compile(prog: Sequence[int], n_operands: int, n_scalars: int, dtype: int) -> None:
+    """Compile a tree outside the catalogue for dtype now (blocking)."""
+    arr, n = _prog(prog)
+    check(lib().salt_jit_compile(arr, n, n_operands, n_scalars, dtype))
+
+
+def salt_jit_code(prog: Sequence[int], n_operands: int, n_scalars: int, dtype: int) -> bytes:
+    """The compiled code object of a tree (b"" if not compiled)."""
+    arr, n = _prog(prog)
+    size = ctypes.c_size_t()
+    check(lib().salt_jit_code(arr, n, n_operands, n_scalars, dtype, None, 0, ctypes.byref(size)))
+    buf = ctypes.create_string_buffer(max(1, size.value))
+    check(lib().salt_jit_code(arr, n, n_operands, n_scalars, dtype, buf, size.value, ctypes.byref(size)))
+    return buf.raw[:size.value]
+
+
+def salt_eval_route(prog: Sequence[int], n_operands: int, n_scalars: int, dtype: int) -> int:
+    """Catalogue index, ROUTE_COMPILED, or -1 (interpreter)."""
+    arr, n = _prog(prog)
+    r = ctypes.c_int32()
+    check(lib().salt_eval_route(arr, n, n_operands, n_scalars, dtype, ctypes.byref(r)))
     return r.value
 
 

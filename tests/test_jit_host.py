@@ -1,0 +1,94 @@
+"""Run-time compilation of trees outside the catalogue, on the host (hipRTC
+needs no GPU): every element type compiles, the code object follows the
+library's build rules (no packed binary32 instructions, no fused multiply-
+add: every add, sub and mul stays one IEEE operation), catalogue trees are
+not compiled again, and the route reflects what is cached. Nothing is
+loaded on a device or launched here."""
+from __future__ import annotations
+
+import os
+import random
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_1109_1264_amd import salt as S
+
+T = S.token
+OBJDUMP = "/opt/rocm/llvm/bin/llvm-objdump"
+DTS = [S.F64, S.F32, S.BF16, S.F16]
+
+
+def rand_prog(rng, nops, nsc, leaves):
+    def build(k):
+        if k == 1:
+            if nsc and rng.random() < 0.25:
+                return [T(S.SCALAR, rng.randrange(nsc))]
+            return [T(S.LOAD, rng.randrange(nops))]
+        m = rng.randrange(1, k)
+        return build(m) + build(k - m) + [T(rng.choice([S.ADD, S.SUB, S.MUL]))]
+    return build(leaves)
+
+
+@pytest.fixture(autouse=True)
+def explicit_mode():
+    S.salt_jit_set_mode(S.JIT_EXPLICIT)
+    yield
+    S.salt_jit_set_mode(S.JIT_AUTO)
+
+
+def disasm(code: bytes, tmp_path) -> str:
+    p = tmp_path / "k.co"
+    p.write_bytes(code)
+    return subprocess.run([OBJDUMP, "-d", str(p)], capture_output=True, text=True, check=True).stdout
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_compiles_and_follows_the_build_rules(dt, tmp_path):
+    # (a*b + c) * (a - e): multiplications next to additions, which
+    # contraction would turn into fused multiply-adds
+    prog = [T(S.LOAD, 0), T(S.LOAD, 1), T(S.MUL), T(S.LOAD, 2), T(S.ADD),
+            T(S.LOAD, 0), T(S.LOAD, 3), T(S.SUB), T(S.MUL)]
+    assert S.salt_eval_route(prog, 4, 0, dt) == -1
+    S.salt_jit_compile(prog, 4, 0, dt)
+    assert S.salt_eval_route(prog, 4, 0, dt) == S.ROUTE_COMPILED
+    code = S.salt_jit_code(prog, 4, 0, dt)
+    assert code[:4] == b"\x7fELF"
+    if not os.path.exists(OBJDUMP):
+        pytest.skip("llvm-objdump not installed")
+    asm = disasm(code, tmp_path)
+    assert "salt_jit_u4_nt" in asm and "salt_jit_u1_c" in asm
+    assert not re.search(r"\bv_pk_(add|mul|fma)_f32\b", asm), "packed binary32 instruction"
+    assert not re.search(r"\bv_(fma|fmac|mad|mac)_(f32|f64|legacy)", asm), "contracted multiply-add"
+    assert re.search(r"\bv_mul_f(32|64)", asm) and re.search(r"\bv_(add|sub)_f(32|64)", asm)
+
+
+def test_random_trees_compile_and_catalogue_trees_are_not_recompiled():
+    rng = random.Random(77)
+    for trial in range(6):
+        nops, nsc = rng.randint(1, 8), rng.randint(0, 3)
+        prog = rand_prog(rng, nops, nsc, rng.randint(2, 7))
+        dt = DTS[trial % 4]
+        S.salt_jit_compile(prog, nops, nsc, dt)
+        r = S.salt_eval_route(prog, nops, nsc, dt)
+        assert r == S.ROUTE_COMPILED or r >= 0, (trial, prog, r)
+    fig1 = [T(S.LOAD, 0), T(S.LOAD, 1), T(S.LOAD, 2), T(S.SUB), T(S.ADD)]
+    S.salt_jit_compile(fig1, 3, 0, S.F64)          # nothing to do
+    assert S.salt_eval_route(fig1, 3, 0, S.F64) == 2
+    assert S.salt_jit_code(fig1, 3, 0, S.F64) == b""
+
+
+def test_modes_and_errors():
+    prog = [T(S.LOAD, 1), T(S.LOAD, 0), T(S.SUB), T(S.SCALAR, 0), T(S.MUL)]
+    S.salt_jit_compile(prog, 2, 1, S.F32)
+    assert S.salt_eval_route(prog, 2, 1, S.F32) == S.ROUTE_COMPILED
+    S.salt_jit_set_mode(S.JIT_OFF)
+    assert S.salt_eval_route(prog, 2, 1, S.F32) == -1      # the interpreter while off
+    with pytest.raises(S.SaltError):
+        S.salt_jit_set_mode(3)
+    with pytest.raises(S.SaltError):
+        S.salt_jit_compile([T(S.ADD)], 1, 0, S.F32)        # malformed program
+    with pytest.raises(S.SaltError):
+        S.salt_jit_compile(prog, 2, 1, 9)                   # unknown dtype
