@@ -32,8 +32,8 @@ def _torch_dtype(d):
 
 
 def candidates(kind: str, n: int, dtype: int, cus: int):
-    unrolls = {"eval": (1, 2, 4, 8), "interp": (1, 2, 4), "batch": (2, 4, 8), "dotx": (2, 4, 8),
-               "nrm2x": (2, 4, 8)}.get(kind, (2, 4, 8, 16))
+    unrolls = {"eval": (1, 2, 4, 8), "interp": (1, 2, 4), "jit": (1, 2, 4), "batch": (2, 4, 8),
+               "dotx": (2, 4, 8), "nrm2x": (2, 4, 8)}.get(kind, (2, 4, 8, 16))
     grids = [0] + [cus * k for k in (1, 2, 4, 8, 16)]
     out = []
     for u in unrolls:
@@ -72,17 +72,21 @@ def time_config(fn, cfg, reps: int, warm: int = 2) -> float:
 
 
 # Representative programs outside the catalogue: they run on the interpreter
-# (eval, route -1) and on the expression reductions (dot / nrm2, route -2).
+# (eval, route -1), on their run-time compiled kernel (eval, route -3) and on
+# the interpreted expression reductions (dot / nrm2, route -2).
 T_ = S.token
 INTERP_PROG = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD), T_(S.LOAD, 2), T_(S.MUL)]   # (a + b) * c
-EXPR_P = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD)]                                  # a + b
-EXPR_Q = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.SUB)]                                  # a - b
+# interpreted expression reductions: a pair outside the reduction catalogue
+EXPR_P = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.MUL)]                                  # a * b
+EXPR_Q = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD)]                                  # a + b
 # The reduction pairs with ahead-of-time kernels (route -16 - index), in the
 # library's catalogue order: (P, Q or None for nrm2).
-PAIRS = [(EXPR_P, EXPR_Q),                                                         # dot(a + b, a - b)
-         (EXPR_Q, None),                                                           # nrm2(a - b)
+_SUM, _DIFF = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD)], [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.SUB)]
+PAIRS = [(_SUM, _DIFF),                                                            # dot(a + b, a - b)
+         (_DIFF, None),                                                            # nrm2(a - b)
          ([T_(S.SCALAR, 0), T_(S.LOAD, 0), T_(S.MUL), T_(S.LOAD, 1), T_(S.ADD)], None)]  # nrm2(alpha*a + b)
 PAIR_ROUTE0 = -16
+JIT_ROUTE = -3   # trees outside the catalogue on their run-time compiled kernels
 
 
 class Workload:
@@ -101,8 +105,9 @@ class Workload:
         td = _torch_dtype(dtype)
         cat = dict(S.salt_catalogue())
         self.route = -1
-        if kind == "interp":
+        if kind in ("interp", "jit"):
             self.prog = INTERP_PROG
+            self.route = -1 if kind == "interp" else JIT_ROUTE
             self.ops = [torch.rand(n_max, device="cuda").to(td) for _ in range(3)]
             self.sc = []
             self.out = torch.empty(n_max, dtype=td, device="cuda")
@@ -175,7 +180,7 @@ class Workload:
         if self.kind == "nrm2x":
             return step(lambda cfg: S.salt_nrm2_expr(EXPR_P, [sl(o) for o in self.ops], [], n=n, result=self.res,
                                                      ws=self.ws, config=cfg))
-        if self.kind in ("eval", "interp"):
+        if self.kind in ("eval", "interp", "jit"):
             return step(lambda cfg: S.salt_eval(self.prog, [sl(o) for o in self.ops], self.sc, sl(self.out),
                                                 config=cfg))
         if self.kind == "dot":
@@ -190,6 +195,13 @@ def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbos
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     w = Workload(kind, tree, dtype, 1 << max(log2ns), rotate=rotate, rotate_from=rotate_from)
+    # the interpreter's rows are timed on the interpreter, the compiled
+    # trees' rows on the compiled kernel
+    if kind == "interp":
+        S.salt_jit_set_mode(S.JIT_OFF)
+    elif kind == "jit":
+        S.salt_jit_set_mode(S.JIT_EXPLICIT)
+        S.salt_jit_compile(w.prog, len(w.ops), 0, dtype)
     rows = []
     for l in log2ns:
         n = 1 << l
@@ -202,13 +214,14 @@ def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbos
                 best = (t, cfg)
         t, (u, nt, b) = best
         gbps = w.arrays * n * S.ELEM_BYTES[dtype] / (t * 1e-3) / 1e9
-        table_kind = {"interp": "eval", "dotx": "dot", "nrm2x": "nrm2"}.get(kind, kind)
+        table_kind = {"interp": "eval", "jit": "eval", "dotx": "dot", "nrm2x": "nrm2"}.get(kind, kind)
         if kind.startswith("pair"):
             table_kind = "nrm2" if PAIRS[w.pair][1] is None else "dot"
         rows.append((table_kind, w.route, dtype, l, u, nt, b, t, gbps))
         if verbose:
             print("tuned %s %s %s 2^%d: unroll=%d nt=%d blocks=%d %.4f ms %.0f GB/s"
                   % (kind, tree or "", S.DTYPE_NAMES[dtype], l, u, nt, b, t, gbps), file=sys.stderr, flush=True)
+    S.salt_jit_set_mode(S.JIT_AUTO)
     return rows
 
 
@@ -301,7 +314,7 @@ def main(argv=None) -> int:
     ap.add_argument("--log2n", default="10-28")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--step", type=int, default=1, help="tune every step-th log2 size")
-    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,dotx,nrm2x,pairs,batch")
+    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,jit,dotx,nrm2x,pairs,batch")
     ap.add_argument("--json", default=None, help="also write all rows as JSON here")
     ap.add_argument("--rotate", action="store_true",
                     help="time working sets of 4 MiB .. 1 GiB streaming from HBM (buffer slices cycled) "
@@ -326,7 +339,7 @@ def main(argv=None) -> int:
         if "eval" in kinds:
             for tree in args.trees.split(","):
                 rows += tune("eval", tree, d, sizes, args.reps, verbose=True, rotate=args.rotate, rotate_from=rf)
-        for kind in ("interp", "dotx", "nrm2x"):
+        for kind in ("interp", "jit", "dotx", "nrm2x"):
             if kind in kinds:
                 rows += tune(kind, None, d, sizes, args.reps, verbose=True, rotate=args.rotate, rotate_from=rf)
         if "pairs" in kinds:

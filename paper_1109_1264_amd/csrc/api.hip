@@ -110,6 +110,8 @@ enum Kind { kEval = 0, kDot = 1, kNrm2 = 2, kBatch = 3 };
 // Tuning-table routes: catalogue trees 0.., the interpreter -1, expression
 // reductions on the interpreter -2, reduction pair id at kRouteRcat0 - id.
 constexpr int kRouteRcat0 = -16;
+// Run-time compiled trees (jit.hip) have their own rows under route -3.
+constexpr int kRouteJit = -3;
 
 struct TuneRow {
     int kind, route, dtype, log2n;
@@ -279,10 +281,20 @@ salt_status eval_impl(const uint32_t *prog, int32_t prog_len, const void *const 
         return device_status(fn(L));
     }
     // a tree outside the catalogue: its run-time compiled kernel when it is
-    // ready, else the interpreter (same bits either way)
-    bool ran = false;
-    const hipError_t je = jit_try_launch(L, p, dtype, &ran);
-    if (ran || je != hipSuccess) return device_status(je);
+    // ready (with the compiled kernels' own tuned knobs), else the
+    // interpreter (same bits either way)
+    if (jit_mode() != kJitOff) {
+        salt_launch_config cj;
+        s = resolve(cfg, lookup(kEval, kRouteJit, dtype, n, p.n_loads + 1), kEval, &cj);
+        if (s != SALT_OK) return s;
+        EvalLaunch LJ = L;
+        LJ.unroll = cj.unroll;
+        LJ.nontemporal = cj.nontemporal;
+        LJ.blocks = cj.blocks;
+        bool ran = false;
+        const hipError_t je = jit_try_launch(LJ, p, dtype, &ran);
+        if (ran || je != hipSuccess) return device_status(je);
+    }
     return device_status(launch_interp(L, p, dtype));
 }
 

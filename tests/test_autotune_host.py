@@ -72,3 +72,12 @@ def test_written_table_reads_back(tmp_path):
         assert S.salt_tuning_lookup(1, A.PAIR_ROUTE0, S.BF16, 1 << 28) == (8, 1, 256)
     finally:
         S.salt_tuning_load(None)
+
+
+def test_tuned_interpreter_programs_stay_on_the_interpreter():
+    """The expression-reduction pair tuned under route -2 is not one with an
+    ahead-of-time kernel, and the eval program tuned under routes -1 and -3
+    is not a catalogue tree."""
+    assert S.salt_reduce_expr_route(A.EXPR_P, A.EXPR_Q, 2, 0) == -1
+    assert S.salt_reduce_expr_route(A.EXPR_P, None, 2, 0) == -1
+    assert S.salt_program_route(A.INTERP_PROG, 3, 0) == -1
