@@ -60,8 +60,11 @@ METRIC = "achieved HBM GB/s (% of peak) on fused vector exprs; served p50/p99 la
 PROFILE_PMC = os.path.join(ROOT, "profiles", "pmc_tree5_f64_n2p28.json")
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print("[%6.1f s]" % (time.perf_counter() - _T0), *a, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
