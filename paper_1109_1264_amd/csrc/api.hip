@@ -501,8 +501,8 @@ salt_status reduce_expr_impl(const uint32_t *px, int32_t lx, const uint32_t *py,
     for (int j = 0; j < n_scalars && j < SALT_MAX_SCALARS; ++j) L.sc[j] = scalars ? scalars[j] : 0.0;
     // A pair with an ahead-of-time kernel runs it (same bits as the
     // interpreter); its tuned knobs live under route kRouteRcat0 - id.
-    int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
-    const int rid = route_pair(px, lx, nrm2 ? nullptr : py, nrm2 ? 0 : ly, om, sm);
+    int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS], nsc = 0;
+    const int rid = route_pair(px, lx, nrm2 ? nullptr : py, nrm2 ? 0 : ly, om, sm, &nsc);
     salt_launch_config c;
     if (rid >= 0) {
         int nl = 0;
@@ -512,7 +512,6 @@ salt_status reduce_expr_impl(const uint32_t *px, int32_t lx, const uint32_t *py,
         ReduceExprLaunch R;
         std::memset(&R, 0, sizeof R);
         for (int k = 0; k < nl; ++k) R.ops[k] = operands[om[k]];
-        const int nsc = gx.n_scal > (nrm2 ? 0 : gy.n_scal) ? gx.n_scal : gy.n_scal;
         for (int j = 0; j < nsc && j < SALT_MAX_SCALARS; ++j) R.sc[j] = scalars[sm[j]];
         R.result = result;
         R.ws = (double *)ws;
@@ -544,8 +543,9 @@ salt_status reduce_expr_impl(const uint32_t *px, int32_t lx, const uint32_t *py,
 
 // Canonical numbering over the concatenation of two validated programs:
 // operands and scalars numbered by first appearance in a, then in b.
-void canon_pair(const uint32_t *a, int32_t la, const uint32_t *b, int32_t lb, uint32_t *ca, uint32_t *cb,
-                int32_t *op_map, int32_t *sc_map) {
+// Returns the number of distinct scalars read.
+int canon_pair(const uint32_t *a, int32_t la, const uint32_t *b, int32_t lb, uint32_t *ca, uint32_t *cb,
+               int32_t *op_map, int32_t *sc_map) {
     int32_t opn[SALT_MAX_OPERANDS], scn[SALT_MAX_SCALARS];
     for (auto &x : opn) x = -1;
     for (auto &x : scn) x = -1;
@@ -564,25 +564,27 @@ void canon_pair(const uint32_t *a, int32_t la, const uint32_t *b, int32_t lb, ui
     };
     for (int i = 0; i < la; ++i) ca[i] = one(a[i]);
     for (int i = 0; i < lb; ++i) cb[i] = one(b[i]);
+    return ns;
 }
 
 }  // namespace
 
 int route_pair(const uint32_t *px, int32_t lx, const uint32_t *py, int32_t ly, int32_t *op_map,
-               int32_t *sc_map) {
+               int32_t *sc_map, int32_t *n_scalars) {
     const auto &cat = rcatalogue();
     for (int order = 0; order < (py ? 2 : 1); ++order) {
         const uint32_t *a = order ? py : px, *b = order ? px : py;
         const int32_t la = order ? ly : lx, lb = py ? (order ? lx : ly) : 0;
         uint32_t ca[SALT_MAX_TOKENS], cb[SALT_MAX_TOKENS];
         int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
-        canon_pair(a, la, b, lb, ca, cb, om, sm);
+        const int ns = canon_pair(a, la, b, lb, ca, cb, om, sm);
         for (size_t id = 0; id < cat.size(); ++id) {
             const RcatEntry &e = cat[id];
             if (e.lp != la || e.lq != lb) continue;
             if (std::memcmp(e.p, ca, sizeof(uint32_t) * la) || std::memcmp(e.q, cb, sizeof(uint32_t) * lb)) continue;
             std::memcpy(op_map, om, sizeof om);
             std::memcpy(sc_map, sm, sizeof sm);
+            if (n_scalars) *n_scalars = ns;
             return (int)id;
         }
     }
@@ -1101,7 +1103,7 @@ salt_status salt_reduce_expr_route(const uint32_t *prog_x, int32_t len_x, const 
         if (s != SALT_OK) return fail(s, "second program: " + why);
     }
     int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
-    if (route) *route = route_pair(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm);
+    if (route) *route = route_pair(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm, nullptr);
     return SALT_OK;
 }
 

@@ -77,10 +77,11 @@ hipError_t launch_reduce_expr(const ReduceExprLaunch &L, const Program &px, cons
 hipError_t launch_reduce_tree(const ReduceExprLaunch &L, int id, int dtype);
 // The reduction pair that (P, Q) is, with operands and scalars renumbered
 // (op_map[k] / sc_map[j]: the caller's index of canonical operand k /
-// scalar j), or -1. Q is null for nrm2. A dot pair also matches with P and
-// Q exchanged (the product is symmetric).
+// scalar j; *n_scalars, if not null, the distinct scalars read), or -1. Q
+// is null for nrm2. A dot pair also matches with P and Q exchanged (the
+// product is symmetric).
 int route_pair(const uint32_t *px, int32_t lx, const uint32_t *py, int32_t ly, int32_t *op_map,
-               int32_t *sc_map);
+               int32_t *sc_map, int32_t *n_scalars);
 
 // The plain read/write stream of salt_stream_reference (stream_ref.hip);
 // *err receives the message of a failure.
