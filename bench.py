@@ -982,9 +982,48 @@ def section_served(args):
     if not args.no_parity:
         out["parity"] = served_parity(V, pool, arena, table, 0.5 * rate_sat, args.served_parity_requests)
         out["served_parity_ok"] = out["parity"]["ok"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = served_cpu_baseline(V, meta)
     del pool, arena, table
     torch.cuda.empty_cache()
     return out
+
+
+def served_cpu_baseline(V, meta, budget_elems: int = 50_000_000):
+    """The oracle serving the same request mix on the host's cores, one
+    request after the other (throughput only): the first requests of a
+    stream of the served mix (same trees, lengths and types), up to
+    `budget_elems` elements, each evaluated on host operands of its length
+    and type (uniform [-1, 1), seeded) with every thread this process may
+    use."""
+    import numpy as np
+
+    import oracle
+    from paper_1109_1264_amd import salt, workloads
+
+    cat = dict(salt.salt_catalogue())
+    sample, total = [], 0
+    for m in meta:
+        if total + m[2] > budget_elems:
+            break
+        sample.append(m)
+        total += m[2]
+    threads = host_threads()
+    log("bench: served CPU baseline, %d requests, %d elements, %d threads" % (len(sample), total, threads))
+    ops = [workloads.uniform(m[2], m[1], 7000 + i, len(m[3])) for i, m in enumerate(sample)]
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        for m, o in zip(sample, ops):
+            oracle.eval_program(cat[m[0]], o, [m[4]], m[1])
+        t = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
+    nbytes = float(V.request_bytes(sample).sum())
+    return {"value": round(len(sample) / t, 1), "unit": "requests/s", "GBps": round(nbytes / t / 1e9, 3),
+            "cores": threads, "kind": "oracle",
+            "sample": "%d requests (%d elements) of the same trees, lengths and type mix, served one after the "
+                      "other by the oracle on host operands" % (len(sample), total)}
 
 
 def served_parity(V, pool, arena, table, rate, count):

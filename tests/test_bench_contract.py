@@ -66,3 +66,18 @@ def test_traffic_is_derived_from_request_counts():
     assert prof["traffic_bytes_per_launch"] == rd + wr
     assert abs(prof["traffic_bytes_per_launch"] / prof["algorithmic_bytes_per_launch"] - 1) < 1e-4
     assert prof["algorithmic_bytes_per_launch"] == 48 * prof["n"]
+
+
+def test_served_cpu_baseline_record():
+    """The oracle's throughput on a served-like request mix: a bounded sample,
+    its thread count and the requests/s unit."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1109_1264_amd import serve as V
+
+    meta = [("fig1", "f32", 5000, [0, 64, 128], 1.5), ("t5", "bf16", 3000, [0] * 6, 0.75),
+            ("axpy", "f64", 4000, [0, 64], 1.25), ("tree5", "f32", 10 ** 9, [0] * 5, 1.0)]
+    rec = bench.served_cpu_baseline(V, meta, budget_elems=20000)
+    assert rec["kind"] == "oracle" and rec["unit"] == "requests/s" and rec["value"] > 0
+    assert rec["cores"] == bench.host_threads()
+    assert rec["sample"].startswith("3 requests (12000 elements)")
