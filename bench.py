@@ -904,21 +904,9 @@ def section_batched(args):
         sg.close()
         sb.close()
         return r
-    # the fixed cost of one graph launch: a graph of one tiny kernel (64
-    # elements copied), timed the same way
-    small = torch.empty(64, dtype=torch.float32, device="cuda")
-    small_out = torch.empty(64, dtype=torch.float32, device="cuda")
-    copy_prog = [salt.token(salt.LOAD, 0)]
-    salt.salt_eval(copy_prog, [small], [], small_out)
-    torch.cuda.synchronize()
-    g_tiny = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g_tiny):
-        salt.salt_eval(copy_prog, [small], [], small_out)
-    t_tiny = event_ms(g_tiny.replay, 20)
-    del g_tiny
     whole_lens = [(int(n) // tile_el) * tile_el for n in lengths]
     ragged_lens = [int(n) % tile_el for n in lengths]
-    split = {"tile_elems": tile_el, "graph_of_one_tiny_kernel_ms": round(t_tiny, 4),
+    split = {"tile_elems": tile_el,
              "whole_tiles_only": sub_batch(whole_lens, True),
              "ragged_tiles_only": sub_batch(ragged_lens, True),
              "all_tiles_no_dot": sub_batch([int(n) for n in lengths], False)}
