@@ -437,7 +437,8 @@ def section_mix(args):
     (2 GiB each, HBM-resident): the plain stream reference (one 16-byte
     chunk per lane, integer xor, no loop) against the library kernel with
     the same mix (catalogue trees reading k operands and writing one; dot,
-    nrm2 and nrm2 of a sum of 3 or 5 operands, reading only). The reference
+    nrm2 and nrm2 of a sum of 3 or 5 operands on its run-time compiled
+    kernel, reading only). The reference
     at 5 reads and 1 write is the ceiling the fused 5-operand tree is held
     to."""
     import torch
@@ -452,6 +453,10 @@ def section_mix(args):
     ws = salt.workspace(n, salt.F64)
     r = torch.empty(1, dtype=torch.float64, device="cuda")
     cat = dict(salt.salt_catalogue())
+    # the sums of operands are not catalogue pairs: their norms run on
+    # kernels compiled at run time for them (compiled here, before timing)
+    for k in (3, 5):
+        salt.salt_jit_compile_reduce(sum_prog(k), None, k, 0, salt.F64)
     lib = {(1, 1): ("copy", lambda: salt.salt_eval(cat["copy"], ins[:1], [], out)),
            (2, 1): ("axpy tree", lambda: salt.salt_eval(cat["axpy"], ins[:2], [1.25], out)),
            (3, 1): ("fig1 tree", lambda: salt.salt_eval(cat["fig1"], ins[:3], [], out)),
@@ -460,8 +465,10 @@ def section_mix(args):
            (6, 1): ("t5 tree", lambda: salt.salt_eval(cat["t5"], ins[:6], [1.25], out)),
            (1, 0): ("nrm2", lambda: salt.salt_nrm2(ins[0], result=r, ws=ws)),
            (2, 0): ("dot", lambda: salt.salt_dot(ins[0], ins[1], result=r, ws=ws)),
-           (3, 0): ("nrm2(a+b+c)", lambda: salt.salt_nrm2_expr(sum_prog(3), ins[:3], [], result=r, ws=ws)),
-           (5, 0): ("nrm2(a+b+c+e+f)", lambda: salt.salt_nrm2_expr(sum_prog(5), ins[:5], [], result=r, ws=ws))}
+           (3, 0): ("nrm2(a+b+c), compiled",
+                    lambda: salt.salt_nrm2_expr(sum_prog(3), ins[:3], [], result=r, ws=ws)),
+           (5, 0): ("nrm2(a+b+c+e+f), compiled",
+                    lambda: salt.salt_nrm2_expr(sum_prog(5), ins[:5], [], result=r, ws=ws))}
     rows = []
     for (R, W), (name, fn) in lib.items():
         nbytes = (R + W) * 8 * n
@@ -592,8 +599,9 @@ def compiled_trees():
 def expression_reductions(args):
     """Trees reduced without being written (Sec. 2's lazy evaluation inside
     a dot product or a norm), n = 2^28, by storage type: the pairs with
-    ahead-of-time kernels against the interpreter running an equivalent
-    pair (b + a for a + b: the same bits), and the same bits checked."""
+    ahead-of-time kernels against an equivalent pair (b + a for a + b: the
+    same bits) on the interpreter and on its run-time compiled kernel, and
+    the same bits checked."""
     import torch
 
     import paper_1109_1264_amd.salt as salt
@@ -616,6 +624,7 @@ def expression_reductions(args):
         rdt = torch.float64 if dt == "f64" else torch.float32
         r1 = torch.empty(1, dtype=rdt, device="cuda")
         r2 = torch.empty(1, dtype=rdt, device="cuda")
+        r3 = torch.empty(1, dtype=rdt, device="cuda")
         rows = {}
         for name, ((px, py), (qx, qy)) in cases.items():
             def run(p, q, r):
@@ -624,13 +633,22 @@ def expression_reductions(args):
                 else:
                     salt.salt_dot_expr(p, q, [a, b], [1.375], result=r, ws=ws)
             t_aot = event_ms(lambda: run(px, py, r1), 10)
-            t_int = event_ms(lambda: run(qx, qy, r2), 10)
+            try:
+                salt.salt_jit_set_mode(salt.JIT_OFF)
+                t_int = event_ms(lambda: run(qx, qy, r2), 10)
+                salt.salt_jit_set_mode(salt.JIT_EXPLICIT)
+                salt.salt_jit_compile_reduce(qx, qy, 2, 1, code)
+                assert salt.salt_reduce_expr_route(qx, qy, 2, 1, code) == salt.ROUTE_COMPILED
+                t_jit = event_ms(lambda: run(qx, qy, r3), 10)
+            finally:
+                salt.salt_jit_set_mode(salt.JIT_AUTO)
             torch.cuda.synchronize()
             gb = lambda t: round(2 * es * n / (t * 1e-3) / 1e9, 1)
             rows[name] = {"ahead_of_time_ms": round(t_aot, 4), "ahead_of_time_GBps": gb(t_aot),
                           "ahead_of_time_pct_of_8TBps": round(100 * 2 * es * n / (t_aot * 1e-3) / 8e12, 1),
                           "interpreter_ms": round(t_int, 4), "interpreter_GBps": gb(t_int),
-                          "same_bits": bool(torch.equal(r1, r2))}
+                          "compiled_ms": round(t_jit, 4), "compiled_GBps": gb(t_jit),
+                          "same_bits": bool(torch.equal(r1, r2) and torch.equal(r1, r3))}
         out[dt] = rows
         del a, b, ws
         torch.cuda.empty_cache()
@@ -1079,8 +1097,8 @@ def launch_only(args) -> None:
     """Launch the named kernels --steps times each and print nothing else
     (for counter collection under rocprofv3). Each spec is
     kind:dtype:log2n, kind one of dot, nrm2 (whole call), dot1, nrm21 (pass 1
-    only), rsum3, rsum5 (nrm2 of the sum of 3 or 5 operands: 3 or 5 read
-    streams and no write), tree5, fig1, axpy, t4, t5, copy (catalogue trees
+    only), rsum3, rsum5 (nrm2 of the sum of 3 or 5 operands on its run-time
+    compiled kernel: 3 or 5 read streams and no write), tree5, fig1, axpy, t4, t5, copy (catalogue trees
     writing a fresh output). Inputs cycle through enough copies that each
     launch reads past the 256 MiB last-level cache."""
     import torch
@@ -1105,6 +1123,8 @@ def launch_only(args) -> None:
         part = torch.empty(max(1, salt.salt_reduce_workspace_bytes(n, code) // 8), dtype=torch.float64,
                            device="cuda")
         out = torch.empty(n, dtype=ops[0][0].dtype, device="cuda") if kind in cat else None
+        if kind in ("rsum3", "rsum5"):
+            salt.salt_jit_compile_reduce(sum_prog(loads), None, loads, 0, code)  # every launch compiled
         for s in range(args.steps):
             v = ops[s % sets]
             if kind == "dot":

@@ -459,15 +459,39 @@ salt_status salt_eval_route(const uint32_t *prog, int32_t prog_len, int32_t n_op
                             int32_t n_scalars, salt_dtype dtype, int32_t *route);
 
 /* Which kernel salt_dot_expr (prog_y non-NULL) or salt_nrm2_expr (prog_y
- * NULL) runs for these programs, without touching the GPU: *route is the
- * index of the pair in the library's catalogue of reduction pairs with
- * ahead-of-time kernels (dot(a + b, a - b), nrm2(a - b), nrm2(alpha*a + b),
- * with any operand and scalar numbering; a dot also with its two programs
- * exchanged), or -1 for the interpreter. Both give the same bits. Programs
- * are validated as in those calls. */
+ * NULL) runs now for these programs in `dtype`, without touching the GPU:
+ * *route is the index of the pair in the library's catalogue of reduction
+ * pairs with ahead-of-time kernels (dot(a + b, a - b), nrm2(a - b),
+ * nrm2(alpha*a + b), with any operand and scalar numbering; a dot also with
+ * its two programs exchanged), SALT_ROUTE_COMPILED when the pair's run-time
+ * compiled kernel is ready, or -1 for the interpreter. All three give the
+ * same bits. Programs are validated as in those calls. */
 salt_status salt_reduce_expr_route(const uint32_t *prog_x, int32_t len_x,
                                    const uint32_t *prog_y, int32_t len_y,
-                                   int32_t n_operands, int32_t n_scalars, int32_t *route);
+                                   int32_t n_operands, int32_t n_scalars, salt_dtype dtype,
+                                   int32_t *route);
+
+/* Reductions of expressions (Sec. 2: a tree evaluated lazily inside a dot
+ * product or a norm) whose pair is not in that catalogue run pass 1 on a
+ * kernel compiled at run time for the pair, from the text of the library's
+ * own pass-1 template, under the same modes and policy as trees in
+ * salt_eval (SALT_JIT_AUTO: compiled at the pair's second call of at least
+ * 65536 elements); pass 2 stays the library's. The cache key is the pair in
+ * canonical numbering (operands and scalars numbered by first appearance in
+ * prog_x, then prog_y) and the element type; a dot and the same dot with
+ * its two programs exchanged share one kernel (the same bits either way).
+ * Compile the pair now (blocking; needs no GPU): SALT_OK also for a pair
+ * with an ahead-of-time kernel; SALT_ERR_UNSUPPORTED with the compiler's
+ * log in salt_last_error() if compilation fails. */
+salt_status salt_jit_compile_reduce(const uint32_t *prog_x, int32_t len_x,
+                                    const uint32_t *prog_y, int32_t len_y,
+                                    int32_t n_operands, int32_t n_scalars, salt_dtype dtype);
+
+/* The cached code object (gfx950 ELF) of a compiled pair, as salt_jit_code. */
+salt_status salt_jit_code_reduce(const uint32_t *prog_x, int32_t len_x,
+                                 const uint32_t *prog_y, int32_t len_y,
+                                 int32_t n_operands, int32_t n_scalars, salt_dtype dtype,
+                                 void *buf, size_t cap, size_t *size);
 
 /* Validate a program without touching the GPU. On success fills
  * *stack_need (maximum stack depth) and *n_loads (distinct operands read)

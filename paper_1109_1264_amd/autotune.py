@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,7 +34,7 @@ def _torch_dtype(d):
 
 def candidates(kind: str, n: int, dtype: int, cus: int):
     unrolls = {"eval": (1, 2, 4, 8), "interp": (1, 2, 4), "jit": (1, 2, 4), "batch": (2, 4, 8),
-               "dotx": (2, 4, 8), "nrm2x": (2, 4, 8)}.get(kind, (2, 4, 8, 16))
+               "dotx": (2, 4, 8), "nrm2x": (2, 4, 8), "dotj": (2, 4, 8), "nrm2j": (2, 4, 8)}.get(kind, (2, 4, 8, 16))
     grids = [0] + [cus * k for k in (1, 2, 4, 8, 16)]
     out = []
     for u in unrolls:
@@ -72,8 +73,9 @@ def time_config(fn, cfg, reps: int, warm: int = 2) -> float:
 
 
 # Representative programs outside the catalogue: they run on the interpreter
-# (eval, route -1), on their run-time compiled kernel (eval, route -3) and on
-# the interpreted expression reductions (dot / nrm2, route -2).
+# (eval, route -1), on their run-time compiled kernel (eval, route -3), on
+# the interpreted expression reductions (dot / nrm2, route -2) and on the
+# expression reductions' run-time compiled kernels (dot / nrm2, route -3).
 T_ = S.token
 INTERP_PROG = [T_(S.LOAD, 0), T_(S.LOAD, 1), T_(S.ADD), T_(S.LOAD, 2), T_(S.MUL)]   # (a + b) * c
 # interpreted expression reductions: a pair outside the reduction catalogue
@@ -119,8 +121,10 @@ class Workload:
             self.ws = S.workspace(n_max, dtype)
             self.res = torch.empty(1, dtype=torch.float64 if dtype == S.F64 else torch.float32, device="cuda")
             self.arrays = 2
-        elif kind in ("dotx", "nrm2x"):
-            self.route = -2
+        elif kind in ("dotx", "nrm2x", "dotj", "nrm2j"):
+            # the same pair on the interpreter (route -2) or on its run-time
+            # compiled kernel (JIT_ROUTE)
+            self.route = -2 if kind.endswith("x") else JIT_ROUTE
             self.ops = [torch.rand(n_max, device="cuda").to(td) for _ in range(2)]
             self.ws = S.workspace(n_max, dtype)
             self.res = torch.empty(1, dtype=torch.float64 if dtype == S.F64 else torch.float32, device="cuda")
@@ -174,10 +178,10 @@ class Workload:
                                                          result=self.res, ws=self.ws, config=cfg))
             return step(lambda cfg: S.salt_dot_expr(px, py, [sl(o) for o in self.ops], [1.25], n=n,
                                                     result=self.res, ws=self.ws, config=cfg))
-        if self.kind == "dotx":
+        if self.kind in ("dotx", "dotj"):
             return step(lambda cfg: S.salt_dot_expr(EXPR_P, EXPR_Q, [sl(o) for o in self.ops], [], n=n,
                                                     result=self.res, ws=self.ws, config=cfg))
-        if self.kind == "nrm2x":
+        if self.kind in ("nrm2x", "nrm2j"):
             return step(lambda cfg: S.salt_nrm2_expr(EXPR_P, [sl(o) for o in self.ops], [], n=n, result=self.res,
                                                      ws=self.ws, config=cfg))
         if self.kind in ("eval", "interp", "jit"):
@@ -197,11 +201,14 @@ def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbos
     w = Workload(kind, tree, dtype, 1 << max(log2ns), rotate=rotate, rotate_from=rotate_from)
     # the interpreter's rows are timed on the interpreter, the compiled
     # trees' rows on the compiled kernel
-    if kind == "interp":
+    if kind in ("interp", "dotx", "nrm2x"):
         S.salt_jit_set_mode(S.JIT_OFF)
     elif kind == "jit":
         S.salt_jit_set_mode(S.JIT_EXPLICIT)
         S.salt_jit_compile(w.prog, len(w.ops), 0, dtype)
+    elif kind in ("dotj", "nrm2j"):
+        S.salt_jit_set_mode(S.JIT_EXPLICIT)
+        S.salt_jit_compile_reduce(EXPR_P, EXPR_Q if kind == "dotj" else None, 2, 0, dtype)
     rows = []
     for l in log2ns:
         n = 1 << l
@@ -214,7 +221,8 @@ def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbos
                 best = (t, cfg)
         t, (u, nt, b) = best
         gbps = w.arrays * n * S.ELEM_BYTES[dtype] / (t * 1e-3) / 1e9
-        table_kind = {"interp": "eval", "jit": "eval", "dotx": "dot", "nrm2x": "nrm2"}.get(kind, kind)
+        table_kind = {"interp": "eval", "jit": "eval", "dotx": "dot", "nrm2x": "nrm2", "dotj": "dot",
+                      "nrm2j": "nrm2"}.get(kind, kind)
         if kind.startswith("pair"):
             table_kind = "nrm2" if PAIRS[w.pair][1] is None else "dot"
         rows.append((table_kind, w.route, dtype, l, u, nt, b, t, gbps))
@@ -298,6 +306,29 @@ def serving_scenarios(seed: int = 11):
     return [np.rint(2.0 ** rng.uniform(8, 24, k)).astype(np.int64) for k in (4, 16, 64, 256)]
 
 
+def read_table(path: str):
+    """Rows of a tuning table, in write_table's tuple form (the ms and GB/s
+    comment figures are 0 where a row has none)."""
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            body, _, note = line.partition("#")
+            f = body.split()
+            if len(f) != 7:
+                continue
+            m = re.match(r"\s*([0-9.]+) ms ([0-9.]+) GB/s", note)
+            t, g = (float(m.group(1)), float(m.group(2))) if m else (0.0, 0.0)
+            rows.append((f[0], int(f[1]), int(f[2]), int(f[3]), int(f[4]), int(f[5]), int(f[6]), t, g))
+    return rows
+
+
+def merged(old, new):
+    """old's rows, with every (kind, route, dtype) that new tunes replaced by
+    new's rows; new rows come last."""
+    keys = {(r[0], r[1], r[2]) for r in new}
+    return [r for r in old if (r[0], r[1], r[2]) not in keys] + list(new)
+
+
 def write_table(rows, path: str) -> None:
     with open(path, "w") as fh:
         fh.write("# libsalt tuning table, written by paper_1109_1264_amd.autotune\n")
@@ -314,7 +345,9 @@ def main(argv=None) -> int:
     ap.add_argument("--log2n", default="10-28")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--step", type=int, default=1, help="tune every step-th log2 size")
-    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,jit,dotx,nrm2x,pairs,batch")
+    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,jit,dotx,nrm2x,dotj,nrm2j,pairs,batch")
+    ap.add_argument("--merge", action="store_true",
+                    help="keep the rows of --out whose (kind, route, dtype) this run does not tune")
     ap.add_argument("--json", default=None, help="also write all rows as JSON here")
     ap.add_argument("--rotate", action="store_true",
                     help="time working sets of 4 MiB .. 1 GiB streaming from HBM (buffer slices cycled) "
@@ -339,7 +372,7 @@ def main(argv=None) -> int:
         if "eval" in kinds:
             for tree in args.trees.split(","):
                 rows += tune("eval", tree, d, sizes, args.reps, verbose=True, rotate=args.rotate, rotate_from=rf)
-        for kind in ("interp", "jit", "dotx", "nrm2x"):
+        for kind in ("interp", "jit", "dotx", "nrm2x", "dotj", "nrm2j"):
             if kind in kinds:
                 rows += tune(kind, None, d, sizes, args.reps, verbose=True, rotate=args.rotate, rotate_from=rf)
         if "pairs" in kinds:
@@ -356,6 +389,8 @@ def main(argv=None) -> int:
             for tree in ("fig1", "axpy", "tree5", "t4", "t5"):
                 rows += tune_batch(tree, DT_NAMES[dname], serving_scenarios(), with_dot=False,
                                    reps=args.reps, verbose=True)
+    if args.merge and os.path.exists(args.out):
+        rows = merged(read_table(args.out), rows)
     write_table(rows, args.out)
     if args.json:
         with open(args.json, "w") as fh:

@@ -32,8 +32,15 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
-    "-I" + INCLUDE, "-I" + CSRC,
+    "-I" + INCLUDE, "-I" + CSRC, "-I" + BUILD_DIR,
 ]
+
+# Headers the run-time compiler (csrc/jit.hip) compiles reduction kernels
+# from: their text is embedded in the library, so a compiled pair runs the
+# same kernel template as the ahead-of-time pairs.
+JIT_HEADERS = [os.path.join(INCLUDE, "salt.h")] + [
+    os.path.join(CSRC, h) for h in ("device.hpp", "expr.hpp", "reduce_common.hpp", "reduce_tree.hpp")]
+JIT_HEADERS_INC = os.path.join(BUILD_DIR, "jit_headers.inc")
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 
 
@@ -48,9 +55,34 @@ def _run(cmd):
     return p
 
 
+def write_jit_headers(path: str = JIT_HEADERS_INC) -> None:
+    """Write the embedded header table that csrc/jit.hip includes: the
+    headers' names and their text as raw string literals."""
+    delim = "SALT_HEADER_TEXT"
+    names, texts = [], []
+    for h in JIT_HEADERS:
+        with open(h) as f:
+            text = f.read()
+        if ")" + delim in text:
+            raise RuntimeError("%s contains the raw-string delimiter" % h)
+        names.append('"%s"' % os.path.basename(h))
+        texts.append('R"%s(%s)%s"' % (delim, text, delim))
+    out = ("// Written by build.py: the headers the run-time compiler builds\n"
+           "// reduction kernels from.\n"
+           "static const int kJitHeaderCount = %d;\n"
+           "static const char *const kJitHeaderNames[] = {%s};\n"
+           "static const char *const kJitHeaderTexts[] = {\n%s};\n"
+           % (len(names), ", ".join(names), ",\n".join(texts)))
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        f.write(out)
+    os.replace(tmp, path)
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source and link ``libsalt.so``; returns its path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
+    write_jit_headers()
     jobs = []
     for src in HIP_SOURCES:
         path = os.path.join(CSRC, src)

@@ -456,6 +456,51 @@ salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, v
     return device_status((hipError_t)fn(L));
 }
 
+int canon_pair(const uint32_t *a, int32_t la, const uint32_t *b, int32_t lb, uint32_t *ca, uint32_t *cb,
+               int32_t *op_map, int32_t *sc_map);
+
+// The pair (P, Q) (Q null: nrm2(P)) of validated programs in canonical
+// numbering, for the run-time compiler; op_map / sc_map as canon_pair's. A
+// dot takes whichever order of its two programs gives the smaller canonical
+// form (the product is symmetric, so both orders give the same bits), so
+// dot(P, Q) and dot(Q, P) share one compiled kernel.
+PairTrees pair_trees(const uint32_t *px, int32_t lx, const uint32_t *py, int32_t ly, int32_t *op_map,
+                     int32_t *sc_map, int *n_scalars) {
+    const auto one = [](const uint32_t *a, int32_t la, const uint32_t *b, int32_t lb, bool nrm2, int32_t *om,
+                        int32_t *sm, int *ns) {
+        PairTrees t;
+        t.nrm2 = nrm2;
+        t.lp = la;
+        t.lq = lb;
+        for (int k = 0; k < SALT_MAX_OPERANDS; ++k) om[k] = -1;
+        *ns = canon_pair(a, la, b, lb, t.p, t.q, om, sm);
+        t.n_loads = 0;
+        while (t.n_loads < SALT_MAX_OPERANDS && om[t.n_loads] >= 0) ++t.n_loads;
+        return t;
+    };
+    int ns = 0;
+    PairTrees t = one(px, lx, py, py ? ly : 0, py == nullptr, op_map, sc_map, &ns);
+    if (py) {
+        int32_t om2[SALT_MAX_OPERANDS], sm2[SALT_MAX_SCALARS];
+        int ns2 = 0;
+        const PairTrees u = one(py, ly, px, lx, false, om2, sm2, &ns2);
+        const auto form = [](const PairTrees &v) {
+            std::vector<uint32_t> f(v.p, v.p + v.lp);
+            f.push_back(0xffffffffu);  // no token has this value: separates P from Q
+            f.insert(f.end(), v.q, v.q + v.lq);
+            return f;
+        };
+        if (form(u) < form(t)) {
+            t = u;
+            ns = ns2;
+            std::memcpy(op_map, om2, sizeof om2);
+            std::memcpy(sc_map, sm2, sizeof sm2);
+        }
+    }
+    if (n_scalars) *n_scalars = ns;
+    return t;
+}
+
 salt_status reduce_expr_impl(const uint32_t *px, int32_t lx, const uint32_t *py, int32_t ly,
                              const void *const *operands, int32_t n_operands, const double *scalars,
                              int32_t n_scalars, int64_t n, void *result, void *ws, size_t ws_bytes, int dtype,
@@ -523,6 +568,48 @@ salt_status reduce_expr_impl(const uint32_t *px, int32_t lx, const uint32_t *py,
         R.nrm2 = nrm2 ? 1 : 0;
         R.stream = stream;
         return device_status(launch_reduce_tree(R, rid, dtype));
+    }
+    // Any other pair: pass 1 on its run-time compiled kernel when that is
+    // ready (knobs under route kRouteJit), with the library's pass 2; the
+    // interpreter otherwise. Same bits either way.
+    if (jit_mode() != kJitOff && n > 0) {
+        int32_t jm[SALT_MAX_OPERANDS], js[SALT_MAX_SCALARS];
+        int jns = 0;
+        const PairTrees t = pair_trees(px, lx, nrm2 ? nullptr : py, nrm2 ? 0 : ly, jm, js, &jns);
+        salt_launch_config cj;
+        s = resolve(cfg, lookup(nrm2 ? kNrm2 : kDot, kRouteJit, dtype, n, t.n_loads), nrm2 ? kNrm2 : kDot, &cj);
+        if (s != SALT_OK) return s;
+        ReduceExprLaunch R;
+        std::memset(&R, 0, sizeof R);
+        for (int k = 0; k < t.n_loads; ++k) R.ops[k] = operands[jm[k]];
+        for (int j = 0; j < jns && j < SALT_MAX_SCALARS; ++j) R.sc[j] = scalars[js[j]];
+        R.result = result;
+        R.ws = (double *)ws;
+        R.n = n;
+        R.vec = vec ? 1 : 0;
+        R.unroll = cj.unroll;
+        R.nontemporal = cj.nontemporal;
+        R.blocks = cj.blocks;
+        R.nrm2 = nrm2 ? 1 : 0;
+        R.stream = stream;
+        bool ran = false;
+        const hipError_t je = jit_try_reduce(R, t, dtype, &ran);
+        if (je != hipSuccess) return device_status(je);
+        if (ran) {
+            const int64_t T = reduce_tile_elems(dtype);
+            const int64_t n_tiles = (n + T - 1) / T;
+            if (n_tiles == 1) return SALT_OK;  // pass 1 stored the result
+            ReduceLaunch P2;
+            std::memset(&P2, 0, sizeof P2);
+            P2.result = result;
+            P2.ws = (double *)ws;
+            P2.n = n;
+            P2.mode = nrm2 ? kModeNrm2 : kModeDot;
+            P2.passes = 2;
+            P2.n_partials = n_tiles;
+            P2.stream = stream;
+            return device_status(launch_reduce(P2, dtype));
+        }
     }
     // Tuned knobs of the expression reductions on the interpreter live under
     // route -2.
@@ -596,6 +683,21 @@ salt_status tuned_config(int kind, int route, int dtype, int64_t n, salt_launch_
     *out = lookup(kind, route, dtype, n, kind == kNrm2 ? 1 : kind == kBatch ? 4 : 2);
     return SALT_OK;
 }
+
+// Validate the programs of a dot (prog_y non-null) or nrm2 of expressions.
+salt_status check_pair(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,
+                       int32_t n_operands, int32_t n_scalars) {
+    Program p;
+    std::string why;
+    salt_status s = compile_program(prog_x, len_x, n_operands, n_scalars, &p, &why);
+    if (s != SALT_OK) return fail(s, "first program: " + why);
+    if (prog_y) {
+        s = compile_program(prog_y, len_y, n_operands, n_scalars, &p, &why);
+        if (s != SALT_OK) return fail(s, "second program: " + why);
+    }
+    return SALT_OK;
+}
+
 
 }  // namespace salt
 
@@ -1093,17 +1195,45 @@ salt_status salt_program_route(const uint32_t *prog, int32_t prog_len, int32_t n
 }
 
 salt_status salt_reduce_expr_route(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,
-                                   int32_t n_operands, int32_t n_scalars, int32_t *route) {
-    Program p;
-    std::string why;
-    salt_status s = compile_program(prog_x, len_x, n_operands, n_scalars, &p, &why);
-    if (s != SALT_OK) return fail(s, "first program: " + why);
-    if (prog_y) {
-        s = compile_program(prog_y, len_y, n_operands, n_scalars, &p, &why);
-        if (s != SALT_OK) return fail(s, "second program: " + why);
-    }
+                                   int32_t n_operands, int32_t n_scalars, salt_dtype dtype, int32_t *route) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    const salt_status s = check_pair(prog_x, len_x, prog_y, len_y, n_operands, n_scalars);
+    if (s != SALT_OK) return s;
     int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
-    if (route) *route = route_pair(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm, nullptr);
+    int r = route_pair(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm, nullptr);
+    if (r < 0 && jit_mode() != kJitOff &&
+        jit_pair_ready(pair_trees(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm, nullptr), dtype))
+        r = SALT_ROUTE_COMPILED;
+    if (route) *route = r;
+    return SALT_OK;
+}
+
+salt_status salt_jit_compile_reduce(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,
+                                    int32_t n_operands, int32_t n_scalars, salt_dtype dtype) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    salt_status s = check_pair(prog_x, len_x, prog_y, len_y, n_operands, n_scalars);
+    if (s != SALT_OK) return s;
+    int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
+    if (route_pair(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm, nullptr) >= 0)
+        return SALT_OK;  // a pair with an ahead-of-time kernel
+    std::string why;
+    s = jit_compile_pair(pair_trees(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm, nullptr), dtype, &why);
+    if (s != SALT_OK) return fail(s, why);
+    return SALT_OK;
+}
+
+salt_status salt_jit_code_reduce(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,
+                                 int32_t n_operands, int32_t n_scalars, salt_dtype dtype, void *buf, size_t cap,
+                                 size_t *size) {
+    if (!dtype_ok(dtype)) return fail(SALT_ERR_ARG, "unknown dtype " + std::to_string((int)dtype));
+    if (!size) return fail(SALT_ERR_ARG, "size pointer is NULL");
+    const salt_status s = check_pair(prog_x, len_x, prog_y, len_y, n_operands, n_scalars);
+    if (s != SALT_OK) return s;
+    int32_t om[SALT_MAX_OPERANDS], sm[SALT_MAX_SCALARS];
+    const std::vector<char> code =
+        jit_pair_code(pair_trees(prog_x, len_x, prog_y, prog_y ? len_y : 0, om, sm, nullptr), dtype);
+    *size = code.size();
+    if (buf && cap >= code.size() && !code.empty()) std::memcpy(buf, code.data(), code.size());
     return SALT_OK;
 }
 

@@ -35,6 +35,29 @@ constexpr int64_t kJitAutoMinElems = (int64_t)1 << 16;
 // HIP source of the kernels for canonical program p in element type dtype.
 std::string jit_source(const Program &p, int dtype);
 
+// A reduction pair in canonical numbering (operands and scalars numbered by
+// first appearance in P, then in Q); Q is empty for nrm2(P).
+struct PairTrees {
+    uint32_t p[SALT_MAX_TOKENS], q[SALT_MAX_TOKENS];
+    int lp = 0, lq = 0;
+    bool nrm2 = false;
+    int n_loads = 0;  // distinct operands read by P and Q
+};
+
+// HIP source of the pair's pass-1 kernels for element type dtype (it
+// includes the embedded headers).
+std::string jit_pair_source(const PairTrees &t, int dtype);
+
+// Launch pass 1 of the pair's compiled kernel if it is compiled (same rules
+// as jit_try_launch); *ran tells whether it did. L holds the pair's
+// canonical operands and scalars, its workspace and result; when the
+// reduction fits one tile, pass 1 stores the result itself, else the caller
+// runs pass 2 over the partials.
+hipError_t jit_try_reduce(const ReduceExprLaunch &L, const PairTrees &t, int dtype, bool *ran);
+salt_status jit_compile_pair(const PairTrees &t, int dtype, std::string *err);
+std::vector<char> jit_pair_code(const PairTrees &t, int dtype);
+int jit_pair_ready(const PairTrees &t, int dtype);
+
 // Launch p's compiled kernel if it is compiled (loading it on the current
 // device first unless the stream is being captured); *ran tells whether it
 // did. In the automatic mode a tree's second large call compiles it first.

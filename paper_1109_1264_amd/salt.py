@@ -99,7 +99,9 @@ def lib() -> ctypes.CDLL:
         "salt_catalogue_count": ([], I32),
         "salt_catalogue_program": ([I32, U32P, I32, ctypes.POINTER(ctypes.c_char_p)], I32),
         "salt_program_route": ([U32P, I32, I32, I32, ctypes.POINTER(I32)], I32),
-        "salt_reduce_expr_route": ([U32P, I32, U32P, I32, I32, I32, ctypes.POINTER(I32)], I32),
+        "salt_reduce_expr_route": ([U32P, I32, U32P, I32, I32, I32, I32, ctypes.POINTER(I32)], I32),
+        "salt_jit_compile_reduce": ([U32P, I32, U32P, I32, I32, I32, I32], I32),
+        "salt_jit_code_reduce": ([U32P, I32, U32P, I32, I32, I32, I32, P, SZ, ctypes.POINTER(SZ)], I32),
         "salt_jit_set_mode": ([I32], I32),
         "salt_jit_compile": ([U32P, I32, I32, I32, I32], I32),
         "salt_jit_code": ([U32P, I32, I32, I32, I32, P, SZ, ctypes.POINTER(SZ)], I32),
@@ -507,14 +509,37 @@ def salt_program_route(prog: Sequence[int], n_operands: int, n_scalars: int) -> 
 
 
 def salt_reduce_expr_route(prog_x: Sequence[int], prog_y: Sequence[int] | None, n_operands: int,
-                           n_scalars: int) -> int:
-    """Reduction-pair catalogue index the expression reduction runs, or -1
-    (the interpreter)."""
+                           n_scalars: int, dtype: int = F64) -> int:
+    """Reduction-pair catalogue index the expression reduction runs in
+    dtype, ROUTE_COMPILED (its run-time compiled kernel), or -1 (the
+    interpreter); prog_y None: nrm2."""
     px, lx = _prog(prog_x)
     py, ly = _prog(prog_y) if prog_y is not None else (None, 0)
     r = ctypes.c_int32()
-    check(lib().salt_reduce_expr_route(px, lx, py, ly, n_operands, n_scalars, ctypes.byref(r)))
+    check(lib().salt_reduce_expr_route(px, lx, py, ly, n_operands, n_scalars, dtype, ctypes.byref(r)))
     return r.value
+
+
+def salt_jit_compile_reduce(prog_x: Sequence[int], prog_y: Sequence[int] | None, n_operands: int,
+                            n_scalars: int, dtype: int) -> None:
+    """Compile the pass-1 kernel of dot(prog_x, prog_y) (prog_y None:
+    nrm2(prog_x)) for dtype now (blocking)."""
+    px, lx = _prog(prog_x)
+    py, ly = _prog(prog_y) if prog_y is not None else (None, 0)
+    check(lib().salt_jit_compile_reduce(px, lx, py, ly, n_operands, n_scalars, dtype))
+
+
+def salt_jit_code_reduce(prog_x: Sequence[int], prog_y: Sequence[int] | None, n_operands: int,
+                         n_scalars: int, dtype: int) -> bytes:
+    """The compiled code object of a reduction pair (b"" if not compiled)."""
+    px, lx = _prog(prog_x)
+    py, ly = _prog(prog_y) if prog_y is not None else (None, 0)
+    size = ctypes.c_size_t()
+    check(lib().salt_jit_code_reduce(px, lx, py, ly, n_operands, n_scalars, dtype, None, 0, ctypes.byref(size)))
+    buf = ctypes.create_string_buffer(max(1, size.value))
+    check(lib().salt_jit_code_reduce(px, lx, py, ly, n_operands, n_scalars, dtype, buf, size.value,
+                                     ctypes.byref(size)))
+    return buf.raw[:size.value]
 
 
 JIT_OFF, JIT_EXPLICIT, JIT_AUTO = 0, 1, 2

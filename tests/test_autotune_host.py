@@ -81,3 +81,23 @@ def test_tuned_interpreter_programs_stay_on_the_interpreter():
     assert S.salt_reduce_expr_route(A.EXPR_P, A.EXPR_Q, 2, 0) == -1
     assert S.salt_reduce_expr_route(A.EXPR_P, None, 2, 0) == -1
     assert S.salt_program_route(A.INTERP_PROG, 3, 0) == -1
+
+
+def test_compiled_pair_kinds_and_merge(tmp_path):
+    """The compiled expression reductions are tuned under route -3 with the
+    interpreter's candidate unrolls, and a merged run replaces only the
+    (kind, route, dtype) groups it tunes."""
+    assert {u for u, _, _ in A.candidates("dotj", 1 << 20, S.F32, 256)} == {2, 4, 8}
+    assert {u for u, _, _ in A.candidates("nrm2j", 1 << 20, S.F32, 256)} == {2, 4, 8}
+    old = [("dot", -2, S.F32, 20, 4, 1, 0, 0.01, 100.0),
+           ("dot", A.JIT_ROUTE, S.F32, 20, 2, 0, 0, 0.02, 50.0),
+           ("dot", A.JIT_ROUTE, S.F64, 20, 2, 0, 0, 0.02, 50.0)]
+    p = tmp_path / "t.txt"
+    A.write_table(old, str(p))
+    back = A.read_table(str(p))
+    assert [r[:7] for r in back] == [r[:7] for r in old]
+    assert abs(back[0][7] - 0.01) < 1e-9 and back[0][8] == 100.0
+    new = [("dot", A.JIT_ROUTE, S.F32, 20, 8, 1, 512, 0.01, 90.0),
+           ("dot", A.JIT_ROUTE, S.F32, 22, 8, 1, 512, 0.03, 95.0)]
+    m = A.merged(back, new)
+    assert [r[:7] for r in m] == [r[:7] for r in (old[0], old[2], new[0], new[1])]

@@ -19,6 +19,12 @@ T = S.token
 DTYPES = ["f64", "f32", "bf16", "f16"]
 
 
+@pytest.fixture(autouse=True)
+def restore_jit_mode():
+    yield
+    S.salt_jit_set_mode(S.JIT_AUTO)
+
+
 def composed(progs, dev, sc, dtype, n):
     import torch
 
@@ -176,8 +182,10 @@ def test_ahead_of_time_pairs(dtype, name):
     import torch
 
     (px, py), (qx, qy) = PAIRS[name]
-    assert S.salt_reduce_expr_route(px, py, 2, 2) == list(PAIRS).index(name)
-    assert S.salt_reduce_expr_route(qx, qy, 2, 2) == -1
+    # the equivalent pair runs on the interpreter (not on a compiled kernel)
+    S.salt_jit_set_mode(S.JIT_OFF)
+    assert S.salt_reduce_expr_route(px, py, 2, 2, CODE[dtype]) == list(PAIRS).index(name)
+    assert S.salt_reduce_expr_route(qx, qy, 2, 2, CODE[dtype]) == -1
     # the interpreter variant of nrm2_diff multiplies by scalar 1 = 1.0 (exact)
     sc = [1.375, 1.0]
     Tt = S.salt_reduce_tile_elems(CODE[dtype])

@@ -2,8 +2,10 @@
 needs no GPU): every element type compiles, the code object follows the
 library's build rules (no packed binary32 instructions, no fused multiply-
 add: every add, sub and mul stays one IEEE operation), catalogue trees are
-not compiled again, and the route reflects what is cached. Nothing is
-loaded on a device or launched here."""
+not compiled again, and the route reflects what is cached. The same for
+reduction pairs (dot and nrm2 of expressions), whose pass-1 kernels are
+compiled from the library's own template. Nothing is loaded on a device or
+launched here."""
 from __future__ import annotations
 
 import os
@@ -92,3 +94,55 @@ def test_modes_and_errors():
         S.salt_jit_compile([T(S.ADD)], 1, 0, S.F32)        # malformed program
     with pytest.raises(S.SaltError):
         S.salt_jit_compile(prog, 2, 1, 9)                   # unknown dtype
+
+
+# A dot pair outside the reduction catalogue: dot(a*b + c, e*alpha).
+PAIR_X = [T(S.LOAD, 0), T(S.LOAD, 1), T(S.MUL), T(S.LOAD, 2), T(S.ADD)]
+PAIR_Y = [T(S.LOAD, 3), T(S.SCALAR, 0), T(S.MUL)]
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_reduction_pairs_compile(dt, tmp_path):
+    assert S.salt_reduce_expr_route(PAIR_X, PAIR_Y, 4, 1, dt) == -1
+    S.salt_jit_compile_reduce(PAIR_X, PAIR_Y, 4, 1, dt)
+    assert S.salt_reduce_expr_route(PAIR_X, PAIR_Y, 4, 1, dt) == S.ROUTE_COMPILED
+    # the dot with its programs exchanged shares the kernel (same bits)
+    assert S.salt_reduce_expr_route(PAIR_Y, PAIR_X, 4, 1, dt) == S.ROUTE_COMPILED
+    # so does any operand and scalar numbering of the same pair
+    rx = [T(S.LOAD, 2), T(S.LOAD, 0), T(S.MUL), T(S.LOAD, 3), T(S.ADD)]
+    ry = [T(S.LOAD, 1), T(S.SCALAR, 1), T(S.MUL)]
+    assert S.salt_reduce_expr_route(rx, ry, 4, 2, dt) == S.ROUTE_COMPILED
+    code = S.salt_jit_code_reduce(PAIR_X, PAIR_Y, 4, 1, dt)
+    assert code[:4] == b"\x7fELF"
+    assert S.salt_jit_code_reduce(PAIR_Y, PAIR_X, 4, 1, dt) == code
+    # six pass-1 variants (2, 4, 8 chunks per burst; cached and streaming)
+    syms = set(re.findall(rb"_ZN4salt13k_reduce_tree[A-Za-z0-9_]+", code))
+    assert len(syms) == 6, syms
+    if not os.path.exists(OBJDUMP):
+        pytest.skip("llvm-objdump not installed")
+    asm = disasm(code, tmp_path)
+    assert not re.search(r"\bv_pk_(add|mul|fma)_f32\b", asm), "packed binary32 instruction"
+
+
+def test_reduction_pair_norm_and_catalogue():
+    nx = [T(S.LOAD, 0), T(S.LOAD, 1), T(S.LOAD, 2), T(S.SUB), T(S.MUL)]     # a * (b - c)
+    assert S.salt_reduce_expr_route(nx, None, 3, 0, S.F32) == -1
+    S.salt_jit_compile_reduce(nx, None, 3, 0, S.F32)
+    assert S.salt_reduce_expr_route(nx, None, 3, 0, S.F32) == S.ROUTE_COMPILED
+    assert S.salt_reduce_expr_route(nx, None, 3, 0, S.F64) == -1          # not compiled for binary64
+    # nrm2(P) and dot(P, P) are different kernels
+    assert S.salt_reduce_expr_route(nx, nx, 3, 0, S.F32) == -1
+    # a pair with an ahead-of-time kernel is not compiled again
+    s, d = [T(S.LOAD, 0), T(S.LOAD, 1), T(S.ADD)], [T(S.LOAD, 0), T(S.LOAD, 1), T(S.SUB)]
+    S.salt_jit_compile_reduce(s, d, 2, 0, S.F64)
+    assert S.salt_reduce_expr_route(s, d, 2, 0, S.F64) == 0
+    assert S.salt_jit_code_reduce(s, d, 2, 0, S.F64) == b""
+    S.salt_jit_set_mode(S.JIT_OFF)
+    assert S.salt_reduce_expr_route(nx, None, 3, 0, S.F32) == -1           # the interpreter while off
+    S.salt_jit_set_mode(S.JIT_EXPLICIT)
+    with pytest.raises(S.SaltError):
+        S.salt_jit_compile_reduce(nx, [T(S.SUB)], 3, 0, S.F32)              # malformed second program
+    with pytest.raises(S.SaltError):
+        S.salt_jit_compile_reduce(nx, None, 3, 0, 9)                        # unknown dtype
+    with pytest.raises(S.SaltError):
+        S.salt_reduce_expr_route(nx, None, 3, 0, 9)
