@@ -1145,6 +1145,29 @@ def launch_only(args) -> None:
         torch.cuda.empty_cache()
 
 
+def mix_ceilings(out: dict) -> None:
+    """The read/write-mix ceilings of the batched and served workloads, from
+    the stream references the mix section measured on this GPU: the batched
+    tree reads 3 operands and writes 1 (its dot reads nothing more); a served
+    request of a tree with k operands moves (k + 1) units per element and
+    the trees are drawn uniformly, so the served ceiling is the byte-weighted
+    harmonic mean of the (k, 1) references."""
+    from paper_1109_1264_amd import serve as V
+
+    refs = {(r[0], r[1]): r[3] for r in out["mix"]["rows"]}
+    b = out.get("batched")
+    if b and (3, 1) in refs:
+        b["mix_ceiling_GBps"] = refs[(3, 1)]
+        b["graph_frac_of_mix_ceiling"] = round(b["graph_GBps"] / refs[(3, 1)], 4)
+    sm = out.get("served_summary")
+    if sm:
+        w = [(V.tree_loads(t) + 1, V.tree_loads(t)) for t in V.TREES]
+        if all((k, 1) in refs for _, k in w):
+            ceil = sum(u for u, _ in w) / sum(u / refs[(k, 1)] for u, k in w)
+            sm["mix_ceiling_GBps"] = round(ceil, 1)
+            sm["saturation_frac_of_mix_ceiling"] = round(sm["saturation_GBps"] / ceil, 4)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1213,6 +1236,8 @@ def main() -> int:
             "p50_ms_at_0.9": sv["poisson"]["0.9"]["p50_ms"], "p99_ms_at_0.9": sv["poisson"]["0.9"]["p99_ms"],
             "p50_ms_at_0.5": sv["poisson"]["0.5"]["p50_ms"], "p99_ms_at_0.5": sv["poisson"]["0.5"]["p99_ms"],
             "served_parity_ok": sv.get("served_parity_ok")}
+    if "mix" in out:
+        mix_ceilings(out)
     if not args.no_cpu_baseline and "main" in sections:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2n)

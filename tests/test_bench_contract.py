@@ -81,3 +81,24 @@ def test_served_cpu_baseline_record():
     assert rec["kind"] == "oracle" and rec["unit"] == "requests/s" and rec["value"] > 0
     assert rec["cores"] == bench.host_threads()
     assert rec["sample"].startswith("3 requests (12000 elements)")
+
+
+def test_mix_ceilings_of_batched_and_served():
+    """The batched workload's ceiling is the 3-read 1-write reference; the
+    served one is the byte-weighted harmonic mean of its trees' (k, 1)
+    references (k + 1 units per element, trees drawn uniformly)."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    rows = [[k, 1, 0.0, 8000.0 - 500.0 * k, 0.0, "", 0.0, 0.0, 0.0] for k in range(1, 7)]
+    out = {"mix": {"rows": rows}, "batched": {"graph_GBps": 5000.0},
+           "served_summary": {"saturation_GBps": 5000.0}}
+    bench.mix_ceilings(out)
+    assert out["batched"]["mix_ceiling_GBps"] == 6500.0
+    assert out["batched"]["graph_frac_of_mix_ceiling"] == round(5000.0 / 6500.0, 4)
+    # fig1 (3 operands), axpy (2), tree5 (5), t4 (4), t5 (6)
+    units = {3: 4, 2: 3, 5: 6, 4: 5, 6: 7}
+    want = sum(units.values()) / sum(u / (8000.0 - 500.0 * k) for k, u in units.items())
+    assert abs(out["served_summary"]["mix_ceiling_GBps"] - want) < 0.06
+    assert out["served_summary"]["saturation_frac_of_mix_ceiling"] == round(
+        5000.0 / out["served_summary"]["mix_ceiling_GBps"], 4)
