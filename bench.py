@@ -877,6 +877,19 @@ def section_batched(args):
     g = bt.graph()
     alg_bytes = 16 * total + 8 * bt.tiles
     t_graph = event_ms(g.launch, 20)
+    # the same two kernels launched directly (no graph), and 20 graph
+    # launches back to back between one pair of events (the device time per
+    # launch once the queue is ahead: no event-to-start latency)
+    t_direct = event_ms(bt.launch, 20)
+    g.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        g.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    t_b2b = e0.elapsed_time(e1) / 20
     # the same work as 4096 separate eval + dot calls
     ws = salt.workspace(1 << 20, salt.F32)
 
@@ -932,6 +945,9 @@ def section_batched(args):
            "length_stats": {"min": int(lengths.min()), "median": int(np.median(lengths)),
                             "max": int(lengths.max()), "sigma_ln": 1.5},
            "graph_ms": round(t_graph, 4), "graph_GBps": round(alg_bytes / (t_graph * 1e-3) / 1e9, 1),
+           "direct_launch_ms": round(t_direct, 4),
+           "graph_back_to_back_ms": round(t_b2b, 4),
+           "graph_back_to_back_GBps": round(alg_bytes / (t_b2b * 1e-3) / 1e9, 1),
            "launch_config": salt.salt_tuning_lookup(3, 5, salt.F32, total),
            "separate_launches_ms": round(t_sep, 3), "speedup_vs_separate": round(t_sep / t_graph, 1),
            "plain_f64_one_kernel_ms": round(t_64, 4),
