@@ -112,6 +112,20 @@ struct Tr<SALT_BF16> {
     }
 };
 
+// A binary32 value the compiler must treat as already computed: it cannot
+// fold the operation that produced it into what consumes it. The narrowing
+// to binary16 needs this: gfx950's mixed-precision fma instructions can
+// multiply binary32 operands and round the exact product straight to
+// binary16, and the compiler forms them from a multiply followed by the
+// conversion (even with contraction off). That rounds once where the
+// arithmetic rounds twice (to binary32, then to binary16), and the results
+// differ in rare halfway cases. An empty asm statement with the value as
+// an in-out register operand costs no instruction.
+__device__ __forceinline__ float opaque_f32(float v) {
+    asm("" : "+v"(v));
+    return v;
+}
+
 // binary16.
 template <>
 struct Tr<SALT_F16> {
@@ -125,16 +139,16 @@ struct Tr<SALT_F16> {
     __device__ __forceinline__ static u32x4 pack(const C *v) {
         f16x8 r;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) r[p] = (_Float16)v[p];
+        for (int p = 0; p < 8; ++p) r[p] = (_Float16)opaque_f32(v[p]);
         return __builtin_bit_cast(u32x4, r);
     }
     __device__ __forceinline__ static C ld1(const void *p, int64_t i) {
         return (float)((const _Float16 *)p)[i];
     }
     __device__ __forceinline__ static void st1(void *p, int64_t i, C v) {
-        ((_Float16 *)p)[i] = (_Float16)v;
+        ((_Float16 *)p)[i] = (_Float16)opaque_f32(v);
     }
-    __device__ __forceinline__ static C round(C v) { return (float)(_Float16)v; }
+    __device__ __forceinline__ static C round(C v) { return (float)(_Float16)opaque_f32(v); }
 };
 
 // 16-byte loads and stores, optionally non-temporal (streaming data that is

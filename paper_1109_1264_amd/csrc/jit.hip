@@ -9,6 +9,7 @@
 #include <mutex>
 #include <thread>
 
+#include "batch.hpp"
 #include "reduce_tree.hpp"
 #include "salt.h"
 
@@ -63,18 +64,19 @@ __device__ __forceinline__ void st1(void *p, long long i, C v) {
     ((unsigned short *)p)[i] = __builtin_bit_cast(unsigned short, (__bf16)v);
 }
 )";
-        default:
+        default:  // the narrowing goes through an opaque value, as in device.hpp
             return R"(typedef float C;
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 constexpr int V = 8;
+__device__ __forceinline__ float opaque_f32(float v) { asm("" : "+v"(v)); return v; }
 __device__ __forceinline__ C get(const u32x4 &c, int p) { return (float)__builtin_bit_cast(f16x8, c)[p]; }
 __device__ __forceinline__ u32x4 pack(const C *v) {
     f16x8 r;
-    for (int p = 0; p < 8; ++p) r[p] = (_Float16)v[p];
+    for (int p = 0; p < 8; ++p) r[p] = (_Float16)opaque_f32(v[p]);
     return __builtin_bit_cast(u32x4, r);
 }
 __device__ __forceinline__ C ld1(const void *p, long long i) { return (float)((const _Float16 *)p)[i]; }
-__device__ __forceinline__ void st1(void *p, long long i, C v) { ((_Float16 *)p)[i] = (_Float16)v; }
+__device__ __forceinline__ void st1(void *p, long long i, C v) { ((_Float16 *)p)[i] = (_Float16)opaque_f32(v); }
 )";
     }
 }
@@ -223,33 +225,63 @@ std::string jit_pair_source(const PairTrees &t, int dtype) {
     return s;
 }
 
+std::string jit_batch_source(const Program &p, int dtype) {
+    (void)dtype;  // the element type is a template argument of the kernels
+    std::string s;
+    s += "// generated by libsalt for one tree in batched launches\n#include \"batch_device.hpp\"\n";
+    s += "namespace salt {\nnamespace jit_batch {\n";
+    s += "using E = " + tree_type(p.canon, p.len) + ";\n";
+    s += "}  // namespace jit_batch\n}  // namespace salt\n";
+    return s;
+}
+
 namespace {
+
+std::string batch_kernel_expr(int dtype, int u, bool nt, bool dot) {
+    return "salt::k_batch<salt::jit_batch::E, " + std::to_string(dtype) + ", " + std::to_string(u) + ", " +
+           (nt ? "true" : "false") + ", " + (dot ? "true" : "false") + ">";
+}
 
 // ---- cache and per-device modules -----------------------------------------
 
 enum State { kNew = 0, kCompiling = 1, kCompiled = 2, kFailed = 3 };
-enum Kind { kKindEval = 0, kKindPair = 1 };
+enum Kind { kKindEval = 0, kKindPair = 1, kKindBatch = 2 };
+
+// Kernel variants of a module: 3 unroll choices x (cached, streaming) x
+// (without, with the batched dot); element-wise trees and reduction pairs
+// use the first half only.
+constexpr int kVariants = 12;
+constexpr int vidx(int ui, bool nt, bool dot) { return (ui * 2 + (nt ? 1 : 0)) * 2 + (dot ? 1 : 0); }
 
 struct Loaded {
     hipModule_t mod = nullptr;
-    hipFunction_t fn[3][2] = {};
+    hipFunction_t fn[kVariants] = {};
 };
 
 struct Entry {
     std::atomic<int> state{kNew};
     int seen = 0;  // large calls that found it not compiled (automatic mode)
     int kind = kKindEval;
-    Program prog;    // an element-wise tree
-    PairTrees pair;  // a reduction pair
+    Program prog;      // an element-wise tree
+    PairTrees pair;    // a reduction pair
+    bool dot = false;  // batched: the variants with the fused dot (else without)
     int dtype = 0;
     std::vector<char> code;
     std::string log;
-    std::string names[3][2];    // kernel symbols, by unroll index and nt
+    std::string names[kVariants];  // kernel symbols by vidx (empty: not built)
     std::map<int, Loaded> dev;  // device -> loaded module
 };
 
 std::string key_of(const Program &p, int dtype) {
     std::string k(1, (char)('0' + dtype));
+    k.append((const char *)p.canon, sizeof(uint32_t) * (size_t)p.len);
+    return k;
+}
+
+std::string batch_key_of(const Program &p, int dtype, bool dot) {
+    std::string k = "b";
+    k += (char)('0' + dtype);
+    k += dot ? 'd' : 'e';
     k.append((const char *)p.canon, sizeof(uint32_t) * (size_t)p.len);
     return k;
 }
@@ -280,8 +312,11 @@ const char kStubStdint[] =
 const char kStubStddef[] = "#pragma once\ntypedef __SIZE_TYPE__ size_t;\ntypedef __PTRDIFF_TYPE__ ptrdiff_t;\n";
 
 bool compile_entry(Entry &e) {
-    const bool pair = e.kind == kKindPair;
-    const std::string src = pair ? jit_pair_source(e.pair, e.dtype) : jit_source(e.prog, e.dtype);
+    // reduction pairs and batched trees are built from the embedded headers
+    const bool pair = e.kind != kKindEval;
+    const std::string src = e.kind == kKindPair    ? jit_pair_source(e.pair, e.dtype)
+                            : e.kind == kKindBatch ? jit_batch_source(e.prog, e.dtype)
+                                                   : jit_source(e.prog, e.dtype);
     std::vector<const char *> hnames, htexts;
     if (pair) {
         hnames = {"hip/hip_runtime.h", "cstdint", "stdint.h", "stddef.h"};
@@ -297,17 +332,24 @@ bool compile_entry(Entry &e) {
         e.log = "hiprtcCreateProgram failed";
         return false;
     }
-    std::string exprs[3][2];
+    // the instantiations to build, by variant (template kernels are named by
+    // expression and looked up by their lowered names after compiling)
+    std::string exprs[kVariants];
     if (pair)
         for (int i = 0; i < 3; ++i)
-            for (int nt = 0; nt < 2; ++nt) {
-                exprs[i][nt] = pair_kernel_expr(e.dtype, kPairUnrolls[i], nt != 0);
-                if (hiprtcAddNameExpression(h, exprs[i][nt].c_str()) != HIPRTC_SUCCESS) {
-                    e.log = "hiprtcAddNameExpression failed";
-                    hiprtcDestroyProgram(&h);
-                    return false;
+            for (int nt = 0; nt < 2; ++nt)
+                for (int dot = 0; dot < 2; ++dot) {
+                    std::string &x = exprs[vidx(i, nt != 0, dot != 0)];
+                    if (e.kind == kKindPair && !dot)
+                        x = pair_kernel_expr(e.dtype, kPairUnrolls[i], nt != 0);
+                    else if (e.kind == kKindBatch && (dot != 0) == e.dot)
+                        x = batch_kernel_expr(e.dtype, kPairUnrolls[i], nt != 0, dot != 0);
+                    if (!x.empty() && hiprtcAddNameExpression(h, x.c_str()) != HIPRTC_SUCCESS) {
+                        e.log = "hiprtcAddNameExpression failed";
+                        hiprtcDestroyProgram(&h);
+                        return false;
+                    }
                 }
-            }
     // the library's own build rules: no contraction, no packed binary32
     const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
@@ -329,13 +371,17 @@ bool compile_entry(Entry &e) {
         for (int i = 0; i < 3 && ok; ++i)
             for (int nt = 0; nt < 2 && ok; ++nt) {
                 if (!pair) {
-                    e.names[i][nt] = entry_name(kUnrolls[i], nt != 0);
+                    e.names[vidx(i, nt != 0, false)] = entry_name(kUnrolls[i], nt != 0);
                     continue;
                 }
-                const char *lowered = nullptr;
-                ok = hiprtcGetLoweredName(h, exprs[i][nt].c_str(), &lowered) == HIPRTC_SUCCESS && lowered;
-                if (ok) e.names[i][nt] = lowered;  // copied before the program is destroyed
-                else e.log += "\nno symbol for " + exprs[i][nt];
+                for (int dot = 0; dot < 2 && ok; ++dot) {
+                    const std::string &x = exprs[vidx(i, nt != 0, dot != 0)];
+                    if (x.empty()) continue;
+                    const char *lowered = nullptr;
+                    ok = hiprtcGetLoweredName(h, x.c_str(), &lowered) == HIPRTC_SUCCESS && lowered;
+                    if (ok) e.names[vidx(i, nt != 0, dot != 0)] = lowered;  // copied before the destroy
+                    else e.log += "\nno symbol for " + x;
+                }
             }
     } else if (e.log.empty()) {
         e.log = hiprtcGetErrorString(r);
@@ -392,14 +438,14 @@ hipError_t loaded_locked(Entry &e, Loaded **out) {
         Loaded l;
         err = hipModuleLoadData(&l.mod, e.code.data());
         if (err != hipSuccess) return err;
-        for (int i = 0; i < 3; ++i)
-            for (int nt = 0; nt < 2; ++nt) {
-                err = hipModuleGetFunction(&l.fn[i][nt], l.mod, e.names[i][nt].c_str());
-                if (err != hipSuccess) {
-                    (void)hipModuleUnload(l.mod);
-                    return err;
-                }
+        for (int v = 0; v < kVariants; ++v) {
+            if (e.names[v].empty()) continue;
+            err = hipModuleGetFunction(&l.fn[v], l.mod, e.names[v].c_str());
+            if (err != hipSuccess) {
+                (void)hipModuleUnload(l.mod);
+                return err;
             }
+        }
         it = e.dev.emplace(dev, l).first;
     }
     *out = &it->second;
@@ -521,7 +567,7 @@ hipError_t launch_jit(const Loaded &l, const EvalLaunch &L, int dtype, int n_loa
     if (g < 1) g = 1;
     if (g > 0x7fffffff) g = 0x7fffffff;
     void *params[] = {&a};
-    return hipModuleLaunchKernel(l.fn[ui][L.nontemporal ? 1 : 0], (unsigned)g, 1, 1, 256, 1, 1, 0,
+    return hipModuleLaunchKernel(l.fn[vidx(ui, L.nontemporal != 0, false)], (unsigned)g, 1, 1, 256, 1, 1, 0,
                                  (hipStream_t)L.stream, params, nullptr);
 }
 
@@ -548,11 +594,93 @@ hipError_t launch_pair(const Loaded &l, const ReduceExprLaunch &L, int n_loads) 
     int64_t grid = L.blocks > 0 && L.blocks < n_tiles ? L.blocks : n_tiles;
     if (grid > 0x7fffffff) grid = 0x7fffffff;
     void *params[] = {&a};
-    return hipModuleLaunchKernel(l.fn[ui][L.nontemporal ? 1 : 0], (unsigned)grid, 1, 1, kBlock, 1, 1, 0,
+    return hipModuleLaunchKernel(l.fn[vidx(ui, L.nontemporal != 0, false)], (unsigned)grid, 1, 1, kBlock, 1, 1, 0,
                                  (hipStream_t)L.stream, params, nullptr);
 }
 
+// The batched kernel of a compiled tree (the template's own argument list),
+// then the library's per-item combine when any item wants its dot.
+hipError_t launch_batch(const Loaded &l, const BatchLaunch &L, int dtype, int n_loads) {
+    // chunks per burst: the knob's unroll, at most 4 with more than four
+    // operands (register budget)
+    int ui = L.unroll >= 8 ? 2 : L.unroll == 4 ? 1 : 0;
+    if (n_loads > 4 && ui > 1) ui = 1;
+    const bool dot = L.any_dot != 0;
+    hipFunction_t f = l.fn[vidx(ui, L.nontemporal != 0, dot)];
+    if (!f) return hipErrorInvalidValue;  // a dot needs two operands (the planner checks it)
+    int64_t grid = L.blocks > 0 && L.blocks < L.total_tiles ? L.blocks : L.total_tiles;
+    if (grid > 0x7fffffff) grid = 0x7fffffff;
+    if (grid > 0) {
+        const DevItem *items = L.items;
+        const TileRef *tiles = L.tiles;
+        int64_t total = L.total_tiles;
+        double *ws = L.ws;
+        void *params[] = {&items, &tiles, &total, &ws};
+        const hipError_t e = hipModuleLaunchKernel(f, (unsigned)grid, 1, 1, kBlock, 1, 1, 0,
+                                                   (hipStream_t)L.stream, params, nullptr);
+        if (e != hipSuccess) return e;
+    }
+    if (!dot) return hipSuccess;
+    BatchFn combine = batch_combine_launcher(dtype);
+    return combine ? (hipError_t)combine(L) : hipErrorInvalidValue;
+}
+
+// The loaded module of a compiled batched tree on the current device;
+// loading is refused while `stream` is being captured (it would not be
+// recorded), and an entry that is not compiled is an error: batched plans
+// compile their tree when they are created.
+hipError_t batch_module(const Program &p, int dtype, bool dot, hipStream_t stream, bool capture_ok,
+                        Loaded **out) {
+    *out = nullptr;
+    Jit &J = jit();
+    std::lock_guard<std::mutex> g(J.mu);
+    Entry *e = find_locked(J, batch_key_of(p, dtype, dot));
+    if (!e || e->state.load() != kCompiled) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (!e->dev.count(dev) && !capture_ok) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        err = hipStreamIsCapturing(stream, &cs);
+        if (err != hipSuccess) return err;
+        if (cs != hipStreamCaptureStatusNone) return hipErrorStreamCaptureUnsupported;
+    }
+    return loaded_locked(*e, out);
+}
+
 }  // namespace
+
+salt_status jit_compile_batch(const Program &p, int dtype, bool dot, std::string *err) {
+    if (dot && p.n_loads < 2) {
+        *err = "a dot needs two operands";
+        return SALT_ERR_UNSUPPORTED;
+    }
+    return compile_now(
+        batch_key_of(p, dtype, dot),
+        [&](Entry &e) {
+            e.kind = kKindBatch;
+            e.prog = p;
+            e.dtype = dtype;
+            e.dot = dot;
+        },
+        err);
+}
+
+hipError_t jit_batch_load(const Program &p, int dtype, bool dot) {
+    Loaded *l = nullptr;
+    return batch_module(p, dtype, dot, nullptr, true, &l);
+}
+
+hipError_t jit_batch_launch(const BatchLaunch &L, const Program &p, int dtype) {
+    Loaded *l = nullptr;
+    const hipError_t err = batch_module(p, dtype, L.any_dot != 0, (hipStream_t)L.stream, false, &l);
+    if (err != hipSuccess) return err;
+    return launch_batch(*l, L, dtype, p.n_loads);
+}
+
+std::vector<char> jit_batch_code(const Program &p, int dtype, bool dot) {
+    return code_of(batch_key_of(p, dtype, dot));
+}
 
 hipError_t jit_try_launch(const EvalLaunch &L, const Program &p, int dtype, bool *ran) {
     *ran = false;
