@@ -325,13 +325,17 @@ typedef struct salt_batch_plan_s *salt_batch_plan;
 typedef struct salt_graph_s *salt_graph;
 
 /* Validate `count` items against one program and element type and build the
- * host side of the descriptor table. The program must be one of the
- * ahead-of-time trees (salt_catalogue_*), else SALT_ERR_UNSUPPORTED; an item
- * with dot_out needs a program whose first two operands read (in postfix
- * order) are operands[0] and operands[1]. Every check of salt_eval applies to
- * every item. Items must not write to memory another item reads or writes.
- * On success *plan owns host memory only; free it with
- * salt_batch_plan_destroy. */
+ * host side of the descriptor table. A catalogue tree (salt_catalogue_*)
+ * runs its ahead-of-time batched kernels; any other tree has the same
+ * kernel template compiled for it here, at plan creation (blocking, a few
+ * seconds the first time per tree and type; cached for the process, same
+ * bits), unless run-time compilation is off (salt_jit_set_mode), which
+ * gives SALT_ERR_UNSUPPORTED, as does a failed compilation (log in
+ * salt_last_error). An item with dot_out needs a program whose first two
+ * operands read (in postfix order) are operands[0] and operands[1]. Every
+ * check of salt_eval applies to every item. Items must not write to memory
+ * another item reads or writes. On success *plan owns host memory only;
+ * free it with salt_batch_plan_destroy. */
 salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len,
                                    int32_t n_operands, int32_t n_scalars,
                                    const salt_batch_item *items, int32_t count,
@@ -351,7 +355,11 @@ salt_status salt_batch_upload(salt_batch_plan plan, void *table, size_t table_by
 
 /* Enqueue the batched kernel (and, when any item has a dot, the per-item
  * combine) on `hip_stream`. `workspace`: device, 8-byte aligned, >= ws_bytes
- * (may be NULL when ws_bytes is 0). cfg NULL = tuned. */
+ * (may be NULL when ws_bytes is 0). cfg NULL = tuned. A plan of a tree
+ * compiled at run time loads its kernels on the current device at its first
+ * launch there; while `hip_stream` is being captured that load is refused
+ * (SALT_ERR_DEVICE): launch it once first, or use salt_batch_graph_create,
+ * which loads before it captures. */
 salt_status salt_batch_launch(salt_batch_plan plan, void *workspace, size_t ws_bytes,
                               void *hip_stream, const salt_launch_config *cfg);
 

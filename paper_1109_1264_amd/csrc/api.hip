@@ -409,7 +409,8 @@ salt_status strided_reduce_impl(int64_t n, const void *x, int64_t incx, const vo
 }  // namespace salt
 
 struct salt_batch_plan_s {
-    int route = -1, dtype = 0, count = 0;
+    int route = -1, dtype = 0, count = 0;  // route: catalogue id, or -3 (compiled at run time)
+    salt::Program prog;                    // the tree, canonical (for a compiled route)
     int64_t total_tiles = 0, total_elems = 0;
     bool any_dot = false;
     std::vector<salt::DevItem> items;
@@ -440,8 +441,11 @@ salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, v
     salt_status s = resolve(cfg, lookup(kBatch, plan->route, plan->dtype, plan->total_elems, 4), kBatch, &c);
     if (s != SALT_OK) return s;
     if (plan->count == 0) return SALT_OK;
-    BatchFn fn = catalogue_batch_launcher(plan->route, plan->dtype);
-    if (!fn) return fail(SALT_ERR_UNSUPPORTED, "no batched kernel for this tree and dtype");
+    BatchFn fn = nullptr;
+    if (plan->route != kRouteJit) {
+        fn = catalogue_batch_launcher(plan->route, plan->dtype);
+        if (!fn) return fail(SALT_ERR_UNSUPPORTED, "no batched kernel for this tree and dtype");
+    }
     BatchLaunch L;
     L.items = (const DevItem *)plan->table;
     L.tiles = (const TileRef *)((const char *)plan->table + sizeof(DevItem) * plan->count);
@@ -453,6 +457,7 @@ salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, v
     L.nontemporal = c.nontemporal;
     L.blocks = c.blocks;
     L.stream = stream;
+    if (plan->route == kRouteJit) return device_status(jit_batch_launch(L, plan->prog, plan->dtype));
     return device_status((hipError_t)fn(L));
 }
 
@@ -998,13 +1003,20 @@ salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len, int32
     std::string why;
     salt_status s = compile_program(prog, prog_len, n_operands, n_scalars, &p, &why);
     if (s != SALT_OK) return fail(s, why);
-    const int route = route_of(p);
-    if (route == kRouteGeneric)
-        return fail(SALT_ERR_UNSUPPORTED, "batched launches need a tree with an ahead-of-time kernel");
+    int route = route_of(p);
+    if (route == kRouteGeneric) {
+        // a tree outside the catalogue: its batched kernels are compiled
+        // below, once the items tell whether any wants its dot
+        if (jit_mode() == kJitOff)
+            return fail(SALT_ERR_UNSUPPORTED,
+                        "batched launches of a tree outside the catalogue need run-time compilation, which is off");
+        route = kRouteJit;
+    }
     const int64_t T = reduce_tile_elems(dtype);
     auto *pl = new (std::nothrow) salt_batch_plan_s;
     if (!pl) return fail(SALT_ERR_ARG, "out of host memory");
     pl->route = route;
+    pl->prog = p;
     pl->dtype = dtype;
     pl->count = count;
     const size_t es = esize(dtype);
@@ -1068,6 +1080,13 @@ salt_status salt_batch_plan_create(const uint32_t *prog, int32_t prog_len, int32
         return fail(SALT_ERR_ARG, "out of host memory");
     }
     pl->total_tiles = tiles;
+    if (route == kRouteJit) {
+        s = jit_compile_batch(p, dtype, pl->any_dot, &why);
+        if (s != SALT_OK) {
+            delete pl;
+            return fail(s, why);
+        }
+    }
     order_tiles(pl->tiles.data(), tiles, pl->items.data(), T);
     pl->table_bytes = round_up(sizeof(DevItem) * (size_t)count + sizeof(TileRef) * (size_t)tiles, 256);
     pl->ws_bytes = pl->any_dot ? sizeof(double) * (size_t)tiles : 0;
@@ -1111,6 +1130,12 @@ salt_status salt_batch_graph_create(salt_batch_plan plan, void *workspace, size_
                                     const salt_launch_config *cfg, salt_graph *graph) {
     if (!graph) return fail(SALT_ERR_ARG, "graph pointer is NULL");
     *graph = nullptr;
+    // a compiled tree's module is loaded before the capture (loading is not
+    // recorded in a graph)
+    if (plan && plan->route == kRouteJit) {
+        const hipError_t le = jit_batch_load(plan->prog, plan->dtype, plan->any_dot);
+        if (le != hipSuccess) return device_status(le);
+    }
     hipStream_t s = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) return device_status(e);

@@ -37,6 +37,21 @@ BatchFn catalogue_batch_multi_launcher(int dtype) {
     }
 }
 
+BatchFn batch_combine_launcher_f64();
+BatchFn batch_combine_launcher_f32();
+BatchFn batch_combine_launcher_bf16();
+BatchFn batch_combine_launcher_f16();
+
+BatchFn batch_combine_launcher(int dtype) {
+    switch (dtype) {
+        case SALT_F64: return batch_combine_launcher_f64();
+        case SALT_F32: return batch_combine_launcher_f32();
+        case SALT_BF16: return batch_combine_launcher_bf16();
+        case SALT_F16: return batch_combine_launcher_f16();
+        default: return nullptr;
+    }
+}
+
 void order_tiles(TileRef *refs, int64_t count, const DevItem *items, int64_t tile_elems) {
     auto weight = [&](const TileRef &r) {
         const int64_t rest = items[r.item].n - (int64_t)r.tile * tile_elems;

@@ -57,5 +57,8 @@ BatchFn catalogue_batch_launcher(int id, int dtype);
 BatchFn catalogue_batch_multi_launcher(int dtype);
 // Number of distinct operands the catalogue tree reads (-1: bad id).
 int catalogue_loads(int id);
+// The per-item combine of the dots' partials alone (after a batched kernel
+// that wrote them), for element type dtype.
+BatchFn batch_combine_launcher(int dtype);
 
 }  // namespace salt

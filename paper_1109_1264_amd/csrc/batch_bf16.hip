@@ -5,4 +5,5 @@
 namespace salt {
 BatchFn batch_launcher_bf16(int id) { return batch_launcher_for<SALT_BF16>(id); }
 BatchFn batch_multi_launcher_bf16() { return &launch_batch_multi<SALT_BF16>; }
+BatchFn batch_combine_launcher_bf16() { return &launch_combine<SALT_BF16>; }
 }  // namespace salt

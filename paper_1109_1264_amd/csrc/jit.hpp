@@ -24,6 +24,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "launch.hpp"
 #include "program.hpp"
 
@@ -57,6 +58,23 @@ hipError_t jit_try_reduce(const ReduceExprLaunch &L, const PairTrees &t, int dty
 salt_status jit_compile_pair(const PairTrees &t, int dtype, std::string *err);
 std::vector<char> jit_pair_code(const PairTrees &t, int dtype);
 int jit_pair_ready(const PairTrees &t, int dtype);
+
+// Batched launches (salt_batch_*) of a tree outside the catalogue: the
+// library's batched kernel template (batch_device.hpp, embedded like the
+// reduction headers) instantiated for the tree, with or without the fused
+// dot (one module each), in every variant of chunks per burst and
+// streaming hints; the per-item combine of the dots is the library's. A
+// batched plan compiles its tree when it is created, so these do not
+// depend on the mode.
+std::string jit_batch_source(const Program &p, int dtype);
+salt_status jit_compile_batch(const Program &p, int dtype, bool dot, std::string *err);
+// Load the compiled tree's module on the current device (outside capture).
+hipError_t jit_batch_load(const Program &p, int dtype, bool dot);
+// Launch the batched kernel (and the combine when L.any_dot) of a compiled
+// tree; loads its module on the current device first, which is refused
+// (hipErrorStreamCaptureUnsupported) while L.stream is being captured.
+hipError_t jit_batch_launch(const BatchLaunch &L, const Program &p, int dtype);
+std::vector<char> jit_batch_code(const Program &p, int dtype, bool dot);
 
 // Launch p's compiled kernel if it is compiled (loading it on the current
 // device first unless the stream is being captured); *ran tells whether it

@@ -67,9 +67,13 @@ def test_tiles_table_and_workspace_sizes():
 def test_planner_rejects():
     base = 1 << 32
     good = [base, base + 2**24, base + 2**25]
-    # interpreter-only program
+    # a tree outside the catalogue while run-time compilation is off
     prog = [T(S.LOAD, 0), T(S.LOAD, 1), T(S.ADD), T(S.LOAD, 2), T(S.SUB)]
-    assert plan(prog, [(10, good, base + 2**26, None)], nsc=0)[0] == S.ERR_UNSUPPORTED
+    S.salt_jit_set_mode(S.JIT_OFF)
+    try:
+        assert plan(prog, [(10, good, base + 2**26, None)], nsc=0)[0] == S.ERR_UNSUPPORTED
+    finally:
+        S.salt_jit_set_mode(S.JIT_AUTO)
     # dot whose operands are not the first two read
     prog = [T(S.SCALAR, 0), T(S.LOAD, 1), T(S.MUL), T(S.LOAD, 0), T(S.LOAD, 2), T(S.SUB), T(S.ADD)]
     st, _ = plan(prog, [(10, good, base + 2**26, base + 2**30)])
@@ -96,3 +100,23 @@ def test_launch_requires_upload():
     assert S.lib().salt_batch_upload(h, base + 16, 1 << 20, None) == S.ERR_ARG   # misaligned table
     assert S.lib().salt_batch_upload(h, base, 16, None) == S.ERR_ARG             # too small
     S.lib().salt_batch_plan_destroy(h)
+
+
+def test_planner_compiles_trees_outside_the_catalogue():
+    """A tree without ahead-of-time kernels gets its batched kernels compiled
+    at plan creation (no GPU needed), with and without the fused dot; the
+    plan's table and workspace are those of any other tree."""
+    base = 1 << 32
+    good = [base, base + 2**24, base + 2**25]
+    prog = [T(S.LOAD, 0), T(S.LOAD, 1), T(S.MUL), T(S.LOAD, 2), T(S.ADD), T(S.SCALAR, 0), T(S.MUL)]
+    assert S.salt_program_route(prog, 3, 1) == -1
+    Tf = S.salt_reduce_tile_elems(S.F32)
+    for dot in (None, base + 2**30):
+        st, h = plan(prog, [(Tf + 3, good, base + 2**26, dot)])
+        assert st == S.OK, S.lib().salt_last_error()
+        tb, wb, tiles = info(h)
+        assert tiles == 2 and wb == (16 if dot else 0)
+        S.lib().salt_batch_plan_destroy(h)
+    # a dot still needs operands 0 and 1 read first
+    prog2 = [T(S.LOAD, 2), T(S.LOAD, 1), T(S.MUL), T(S.LOAD, 0), T(S.ADD)]
+    assert plan(prog2, [(10, good, base + 2**26, base + 2**30)], nsc=0)[0] == S.ERR_UNSUPPORTED

@@ -182,3 +182,110 @@ def test_c4_full_size():
     check(items, host, dtype, alone_dot=True)
     g.close()
     b.close()
+
+
+# ---- trees outside the catalogue (batched kernels compiled at plan creation) --
+
+L0, L1, L2, L3, L4, L5 = (T(S.LOAD, k) for k in range(6))
+SC0 = T(S.SCALAR, 0)
+ADD, SUB, MUL = T(S.ADD), T(S.SUB), T(S.MUL)
+COMPILED_TREES = [
+    ([L0, L1, MUL, L2, ADD, SC0, MUL], 3, 1),                                  # (a*b + c)*alpha
+    ([L0, L1, SUB, L0, MUL, L2, L3, MUL, SUB], 4, 0),                          # (a - b)*a - c*e
+    ([L0, L1, ADD, L2, L3, ADD, MUL, L4, L5, SUB, MUL, SC0, SUB], 6, 1),       # six operands
+]
+
+
+def make_tree_batch(prog, nops, nsc, dtype, lengths, seed, dot_every=2, offsets=(0,)):
+    import torch
+
+    items, host = [], []
+    for i, n in enumerate(lengths):
+        ops = workloads.uniform(int(n), dtype, seed + i, nops)
+        sc = [workloads.alpha(seed + i)] * nsc
+        off = offsets[i % len(offsets)]
+        dev = [to_dev(v, dtype, offset=off) for v in ops]
+        out = empty(int(n), dtype, offset=off)
+        dot = (torch.empty(1, dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda")
+               if i % dot_every == 0 else None)
+        items.append({"n": int(n), "operands": dev, "scalars": sc, "out": out, "dot_out": dot})
+        host.append((ops, sc))
+    return items, host
+
+
+def check_tree_batch(prog, items, host, dtype):
+    import torch
+
+    torch.cuda.synchronize()
+    for i, (it, (ops, sc)) in enumerate(zip(items, host)):
+        want = oracle_bits(oracle.eval_program(prog, ops, sc, dtype), dtype)
+        got = to_host_bits(it["out"], dtype)
+        assert np.array_equal(got, want), (i, it["n"], first_mismatch(got, want))
+        if it["dot_out"] is not None:
+            got_dot = float(it["dot_out"].item())
+            r = S.salt_dot(it["operands"][0], it["operands"][1], n=it["n"])
+            torch.cuda.synchronize()
+            assert float(r.item()) == got_dot, (i, it["n"])
+            ref, abs_sum = oracle.dot2(oracle.widen(ops[0], dtype), oracle.widen(ops[1], dtype))
+            assert abs(got_dot - ref) <= oracle.TOL[dtype] * abs_sum, (i, it["n"], got_dot, ref)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_compiled_tree_batches(dtype):
+    """Each tree outside the catalogue, batched over ragged and unaligned
+    items with a fused dot on every other item: bit-exact against the oracle,
+    dots with the bits of salt_dot alone; then a graph of the same plan
+    replays the same bits."""
+    import torch
+
+    for k, (prog, nops, nsc) in enumerate(COMPILED_TREES):
+        assert S.salt_program_route(prog, nops, nsc) == -1
+        lengths = ragged_lengths(dtype, 24, seed=11 + k)
+        items, host = make_tree_batch(prog, nops, nsc, dtype, lengths, 2100 + 100 * k, offsets=(0, 0, 1))
+        print("compiled tree batch", dtype, k, len(items), "items", flush=True)
+        b = Batch(prog, items, CODE[dtype])
+        b.launch()
+        check_tree_batch(prog, items, host, dtype)
+        ref_out = [to_host_bits(it["out"], dtype) for it in items]
+        ref_dot = [None if it["dot_out"] is None else float(it["dot_out"].item()) for it in items]
+        g = b.graph()
+        for rep in range(2):
+            for it in items:
+                it["out"].zero_()
+                if it["dot_out"] is not None:
+                    it["dot_out"].fill_(-1.0)
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            for i, it in enumerate(items):
+                assert np.array_equal(to_host_bits(it["out"], dtype), ref_out[i]), (k, rep, i)
+                if ref_dot[i] is not None:
+                    assert float(it["dot_out"].item()) == ref_dot[i], (k, rep, i)
+        g.close()
+        b.close()
+
+
+def test_compiled_tree_batch_launch_shapes():
+    """Every launch knob of a compiled batched tree gives the same bits."""
+    import torch
+
+    dtype = "f32"
+    prog, nops, nsc = COMPILED_TREES[2]
+    items, host = make_tree_batch(prog, nops, nsc, dtype, ragged_lengths(dtype, 20, seed=21), 2600)
+    b = Batch(prog, items, CODE[dtype])
+    b.launch()
+    check_tree_batch(prog, items, host, dtype)
+    ref_out = [to_host_bits(it["out"], dtype) for it in items]
+    ref_dot = [None if it["dot_out"] is None else float(it["dot_out"].item()) for it in items]
+    for unroll in (2, 4, 8):
+        for nt in (0, 1):
+            for blocks in (0, 1, 7, 256):
+                for it in items:
+                    it["out"].zero_()
+                b.launch(config=(unroll, nt, blocks))
+                torch.cuda.synchronize()
+                for i, it in enumerate(items):
+                    assert np.array_equal(to_host_bits(it["out"], dtype), ref_out[i]), (unroll, nt, blocks, i)
+                    if ref_dot[i] is not None:
+                        assert float(it["dot_out"].item()) == ref_dot[i], (unroll, nt, blocks, i)
+    b.close()
