@@ -402,6 +402,11 @@ typedef struct {
                               * launch per tree; 2 one per tree when the
                               * type's requests in the batch hold at least
                               * SALT_SERVE_SPLIT_ELEMS elements, else mixed */
+    const salt_launch_config *launch; /* knobs of every batched launch, as
+                              * for salt_eval_ex (unroll 0, nontemporal -1,
+                              * blocks -1: tuned), or NULL: all tuned, per
+                              * launch by its tree, type and size; unroll
+                              * 2, 4 or 8 (a mixed-tree launch runs 8 as 4) */
 } salt_server_config;
 #define SALT_SERVE_SPLIT_ELEMS ((int64_t)1 << 26)
 

@@ -113,6 +113,12 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
     if (cfg->n_streams < 1 || cfg->n_streams > 8) return bad("n_streams outside 1..8");
     if (cfg->depth < 1 || cfg->depth > 4) return bad("depth outside 1..4");
     if (cfg->grouping < 0 || cfg->grouping > 2) return bad("grouping outside 0..2");
+    if (const salt_launch_config *k = cfg->launch) {
+        if (k->unroll != 0 && k->unroll != 2 && k->unroll != 4 && k->unroll != 8)
+            return bad("launch unroll must be 0, 2, 4 or 8");
+        if (k->nontemporal < -1 || k->nontemporal > 1) return bad("launch nontemporal outside -1..1");
+        if (k->blocks < -1) return bad("launch blocks below -1");
+    }
     const int n_slots = cfg->n_streams * cfg->depth;
     const size_t slot_cap = cfg->table_bytes / n_slots / kAlign * kAlign;
     if (slot_cap < 64 * 1024) return bad("table arena too small for the streams and depth");
@@ -357,6 +363,11 @@ salt_status serve_trace_impl(const salt_server_config *cfg, const salt_request *
                         c.unroll = 4;
                         c.nontemporal = 1;
                         c.blocks = 0;
+                    }
+                    if (const salt_launch_config *k = cfg->launch) {  // the caller's knobs
+                        if (k->unroll != 0) c.unroll = k->unroll;
+                        if (k->nontemporal >= 0) c.nontemporal = k->nontemporal;
+                        if (k->blocks >= 0) c.blocks = k->blocks;
                     }
                     if (g.tree < 0 && c.unroll != 2) c.unroll = 4;
                     BatchLaunch L;

@@ -129,6 +129,25 @@ def test_bad_config_is_rejected(pool):
     assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # table too small
     cfg = V.ServerConfig(arena.data_ptr(), 1 << 20, table.data_ptr(), 4 << 20, 16, 2, 8, 1, 1, 3)
     assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG      # grouping 3
+    for bad in ((3, -1, -1), (4, 2, -1), (4, 1, -2)):                             # launch knobs
+        k = S.LaunchConfig(*bad)
+        cfg = V.ServerConfig(arena.data_ptr(), 1 << 20, table.data_ptr(), 4 << 20, 16, 2, 8, 1, 1, 0,
+                             ctypes.pointer(k))
+        assert L.salt_serve_trace(ctypes.byref(cfg), trace, 3, res) == S.ERR_ARG, bad
+
+
+@pytest.mark.parametrize("launch", [(2, 1, 256), (8, 0, 0), (4, -1, 1)])
+def test_caller_launch_knobs_keep_the_bits(pool, orc, launch):
+    """The caller's launch knobs (unroll, hints, grid) for every batched
+    launch change no result bit."""
+    import torch
+
+    arena, table = V.default_buffers(arena_bytes=1 << 30, table_bytes=16 << 20)
+    trace, meta = V.make_trace(pool, 200, seed=5011, rate=20000.0, lo=8, hi=17)
+    res = V.serve(trace, arena, table, n_streams=2, max_batch=32, keep_outputs=True, launch=launch)
+    torch.cuda.synchronize()
+    assert all(r.status == 0 for r in res)
+    assert check_against_oracle(orc, pool, arena, res, meta, full=True) == sum(m[2] for m in meta)
 
 
 def test_waits_for_callers_queued_work(pool, orc):
