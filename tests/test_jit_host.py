@@ -146,3 +146,34 @@ def test_reduction_pair_norm_and_catalogue():
         S.salt_jit_compile_reduce(nx, None, 3, 0, 9)                        # unknown dtype
     with pytest.raises(S.SaltError):
         S.salt_reduce_expr_route(nx, None, 3, 0, 9)
+
+
+def test_concurrent_compiles_of_one_key():
+    """Threads compiling the same tree or pair at once: one compiles, the
+    others wait for it; all see the same code object."""
+    import threading
+
+    prog = [T(S.LOAD, 2), T(S.LOAD, 0), T(S.SUB), T(S.LOAD, 1), T(S.MUL), T(S.SCALAR, 0), T(S.ADD)]
+    px = [T(S.LOAD, 0), T(S.LOAD, 2), T(S.MUL), T(S.LOAD, 1), T(S.SUB)]
+    errors, codes = [], []
+
+    def work(k):
+        try:
+            if k % 2:
+                S.salt_jit_compile(prog, 3, 1, S.BF16)
+                codes.append(("e", S.salt_jit_code(prog, 3, 1, S.BF16)))
+            else:
+                S.salt_jit_compile_reduce(px, None, 3, 0, S.F32)
+                codes.append(("r", S.salt_jit_code_reduce(px, None, 3, 0, S.F32)))
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(6)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for kind in ("e", "r"):
+        got = [c for k, c in codes if k == kind]
+        assert len(got) == 3 and got[0][:4] == b"\x7fELF" and all(c == got[0] for c in got)
