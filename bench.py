@@ -68,8 +68,10 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the tree kernel's sources (the template, its element types and
+    tree nodes, and its launcher)."""
     h = hashlib.sha256()
-    for f in ("eval.hip", "device.hpp", "expr.hpp"):
+    for f in ("eval_tree.hpp", "device.hpp", "expr.hpp", "eval.hip"):
         with open(os.path.join(ROOT, "paper_1109_1264_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -35,13 +35,12 @@ HIPCC_FLAGS = [
     "-I" + INCLUDE, "-I" + CSRC, "-I" + BUILD_DIR,
 ]
 
-# Headers the run-time compiler (csrc/jit.hip) compiles reduction and
-# batched kernels from: their text is embedded in the library, so a compiled
-# pair or batched tree runs the same kernel template as the ahead-of-time
-# ones.
+# Headers the run-time compiler (csrc/jit.hip) compiles kernels from: their
+# text is embedded in the library, so a compiled tree, reduction pair or
+# batched tree runs the same kernel template as the ahead-of-time ones.
 JIT_HEADERS = [os.path.join(INCLUDE, "salt.h")] + [
-    os.path.join(CSRC, h) for h in ("device.hpp", "expr.hpp", "reduce_common.hpp", "reduce_tree.hpp",
-                                    "batch.hpp", "batch_device.hpp")]
+    os.path.join(CSRC, h) for h in ("device.hpp", "expr.hpp", "eval_tree.hpp", "reduce_common.hpp",
+                                    "reduce_tree.hpp", "batch.hpp", "batch_device.hpp")]
 JIT_HEADERS_INC = os.path.join(BUILD_DIR, "jit_headers.inc")
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 

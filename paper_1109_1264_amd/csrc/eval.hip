@@ -13,91 +13,20 @@
 // scalar tail (Listing 2) and its non-specialised fallback.
 //
 // Two kernel families:
-//  * k_eval_tree<E, ...>: the tree E is a compile-time type (expr.hpp) and the
-//    kernel is straight-line code for it (ahead-of-time catalogue).
+//  * k_eval_tree<E, ...> (eval_tree.hpp): the tree E is a compile-time type
+//    (expr.hpp) and the kernel is straight-line code for it (ahead-of-time
+//    catalogue here; any other tree compiled at run time by jit.hip).
 //  * k_eval_interp<...>: any valid program. The program is uniform across the
 //    grid, so its instruction loop runs on the scalar unit; the top of the
 //    per-lane stack stays in registers and the rest lives in LDS
 //    (interp.hpp).
 #include "device.hpp"
+#include "eval_tree.hpp"
 #include "expr.hpp"
 #include "interp.hpp"
 #include "launch.hpp"
 
 namespace salt {
-
-template <int DT>
-struct EvalArgs {
-    const void *ops[SALT_MAX_OPERANDS];
-    typename Tr<DT>::C sc[SALT_MAX_SCALARS];
-    void *out;
-    int64_t n;
-    int32_t vec;  // 1: 16-byte path for whole tiles; 0: per-element path only
-};
-
-// Operand values of one lane's tile: element p of chunk u of operand K.
-template <int DT, int NL, int U, int NS>
-struct ChunkCtx {
-    using C = typename Tr<DT>::C;
-    const u32x4 (&raw)[NL][U];
-    const C (&s)[NS];
-    int u, p;
-    template <int K>
-    __device__ __forceinline__ C ld() const { return Tr<DT>::get(raw[K][u], p); }
-    template <int J>
-    __device__ __forceinline__ C sc() const { return s[J]; }
-};
-
-// Operand values of one element, loaded one by one.
-template <int DT, int NL, int NS>
-struct ElemCtx {
-    using C = typename Tr<DT>::C;
-    const void *const (&op)[NL];
-    const C (&s)[NS];
-    int64_t i;
-    template <int K>
-    __device__ __forceinline__ C ld() const { return Tr<DT>::ld1(op[K], i); }
-    template <int J>
-    __device__ __forceinline__ C sc() const { return s[J]; }
-};
-
-template <class E, int DT, int U, bool NT>
-__global__ __launch_bounds__(kBlock) void k_eval_tree(EvalArgs<DT> a) {
-    using C = typename Tr<DT>::C;
-    constexpr int V = Tr<DT>::V;
-    constexpr int NL = E::n_loads > 0 ? E::n_loads : 1;
-    constexpr int NS = E::n_scal > 0 ? E::n_scal : 1;
-    const void *op[NL];
-#pragma unroll
-    for (int k = 0; k < NL; ++k) op[k] = a.ops[k];
-    C s[NS];
-#pragma unroll
-    for (int j = 0; j < NS; ++j) s[j] = a.sc[j];
-
-    constexpr int64_t tile = (int64_t)kBlock * U * V;
-    const int64_t n_tiles = a.vec ? a.n / tile : 0;
-    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const int64_t c0 = t * (kBlock * U) + threadIdx.x;  // this lane's first chunk
-        u32x4 raw[NL][U];
-#pragma unroll
-        for (int k = 0; k < E::n_loads; ++k)
-#pragma unroll
-            for (int u = 0; u < U; ++u) raw[k][u] = ld16<NT>((const u32x4 *)op[k] + c0 + u * kBlock);
-        u32x4 res[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            C r[V];
-#pragma unroll
-            for (int p = 0; p < V; ++p) r[p] = E::ev(ChunkCtx<DT, NL, U, NS>{raw, s, u, p});
-            res[u] = Tr<DT>::template pack<V>(r);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) st16<NT>((u32x4 *)a.out + c0 + u * kBlock, res[u]);
-    }
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = n_tiles * tile + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += stride)
-        Tr<DT>::st1(a.out, i, E::ev(ElemCtx<DT, NL, NS>{op, s, i}));
-}
 
 // ---------------------------------------------------------------------------
 // generic interpreter (interp.hpp)
@@ -148,9 +77,7 @@ static EvalArgs<DT> make_args(const EvalLaunch &L) {
     return a;
 }
 
-template <int DT>
-static dim3 grid_for(const EvalLaunch &L, int U) {
-    const int64_t tile = (int64_t)kBlock * U * Tr<DT>::V;
+int64_t eval_grid(const EvalLaunch &L, int64_t tile) {
     const int64_t n_tiles = L.vec ? L.n / tile : 0;
     int64_t g;
     if (n_tiles > 0) {
@@ -162,7 +89,12 @@ static dim3 grid_for(const EvalLaunch &L, int U) {
     }
     if (g < 1) g = 1;
     if (g > 0x7fffffff) g = 0x7fffffff;
-    return dim3((unsigned)g);
+    return g;
+}
+
+template <int DT>
+static dim3 grid_for(const EvalLaunch &L, int U) {
+    return dim3((unsigned)eval_grid(L, (int64_t)kBlock * U * Tr<DT>::V));
 }
 
 template <class E, int DT, int U, bool NT>

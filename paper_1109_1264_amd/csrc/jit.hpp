@@ -2,15 +2,16 @@
 //
 // The paper builds every expression tree at compile time (Sec. 2); a tree
 // that only arrives at run time would otherwise run on the interpreter. Here
-// its canonical postfix form is turned into HIP source for the same loop as
-// the catalogue kernels (load bursts, the tree as straight-line code, store
-// bursts, per-element tail), compiled for gfx950 with hipRTC (contraction
-// off, packed binary32 instructions off, as the library itself is built),
-// cached per (tree, element type), loaded per device on first use and
+// its canonical postfix form becomes a tree type of expr.hpp, and hipRTC
+// instantiates the library's own element-wise kernel template for it
+// (eval_tree.hpp, whose text and that of the headers it includes are
+// embedded in the library at build time) for gfx950, with the library's
+// build rules (contraction off, packed binary32 instructions off). The code
+// is cached per (tree, element type), loaded per device on first use and
 // launched instead of the interpreter. Same operations in the same order:
 // the results are bit-identical to the interpreter's and the oracle's.
 //
-// Compiling takes a fraction of a second, so in the automatic mode a tree
+// Compiling takes about a second, so in the automatic mode a tree
 // runs on the interpreter at its first call of at least kJitAutoMinElems
 // elements and is compiled (on the calling thread) at its second, which then
 // runs the compiled kernel, as do all later calls: a tree used once costs
@@ -33,7 +34,8 @@ namespace salt {
 enum JitMode { kJitOff = 0, kJitExplicit = 1, kJitAuto = 2 };
 constexpr int64_t kJitAutoMinElems = (int64_t)1 << 16;
 
-// HIP source of the kernels for canonical program p in element type dtype.
+// HIP source of the kernels for canonical program p (it includes the
+// embedded headers and names the tree's type).
 std::string jit_source(const Program &p, int dtype);
 
 // A reduction pair in canonical numbering (operands and scalars numbered by

@@ -27,6 +27,11 @@ struct EvalLaunch {
 
 using EvalFn = hipError_t (*)(const EvalLaunch &);
 
+// Grid of an element-wise launch whose tiles hold `tile` elements: one
+// workgroup per whole tile (or L.blocks of them, grid-stride), else enough
+// for the per-element loop (at most 8192 or L.blocks).
+int64_t eval_grid(const EvalLaunch &L, int64_t tile);
+
 // Ahead-of-time kernel launcher for catalogue tree `id` and `dtype`, or null.
 EvalFn catalogue_launcher(int id, int dtype);
 // Postfix form of catalogue tree `id` (canonical numbering) and its name;
