@@ -234,8 +234,10 @@ def tune(kind: str, tree: str | None, dtype: int, log2ns, reps: int = 10, verbos
 
 
 class BatchWorkload:
-    """A batched launch of one catalogue tree over items of the given lengths
-    (operands carved from flat device buffers at 64-element boundaries)."""
+    """A batched launch of one catalogue tree (or, for tree "compiled", of
+    the representative tree outside the catalogue, whose batched kernels are
+    compiled at plan creation) over items of the given lengths (operands
+    carved from flat device buffers at 64-element boundaries)."""
 
     def __init__(self, tree: str, dtype: int, lengths, with_dot: bool, seed: int = 1):
         import numpy as np
@@ -244,8 +246,11 @@ class BatchWorkload:
         from .batch import Batch
 
         td = _torch_dtype(dtype)
-        prog = dict(S.salt_catalogue())[tree]
-        self.route = [name for name, _ in S.salt_catalogue()].index(tree)
+        if tree == "compiled":
+            prog, self.route = INTERP_PROG, JIT_ROUTE
+        else:
+            prog = dict(S.salt_catalogue())[tree]
+            self.route = [name for name, _ in S.salt_catalogue()].index(tree)
         nops = 1 + max([t >> 8 for t in prog if t & 0xFF == S.LOAD], default=-1)
         offs = np.zeros(len(lengths) + 1, dtype=np.int64)
         offs[1:] = np.cumsum((np.asarray(lengths) + 63) // 64 * 64)
@@ -345,7 +350,7 @@ def main(argv=None) -> int:
     ap.add_argument("--log2n", default="10-28")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--step", type=int, default=1, help="tune every step-th log2 size")
-    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,jit,dotx,nrm2x,dotj,nrm2j,pairs,batch")
+    ap.add_argument("--kinds", default="eval,dot,nrm2,interp,jit,dotx,nrm2x,dotj,nrm2j,pairs,batch,batchj")
     ap.add_argument("--merge", action="store_true",
                     help="keep the rows of --out whose (kind, route, dtype) this run does not tune")
     ap.add_argument("--json", default=None, help="also write all rows as JSON here")
@@ -389,6 +394,10 @@ def main(argv=None) -> int:
             for tree in ("fig1", "axpy", "tree5", "t4", "t5"):
                 rows += tune_batch(tree, DT_NAMES[dname], serving_scenarios(), with_dot=False,
                                    reps=args.reps, verbose=True)
+    if "batchj" in kinds:  # batched launches of compiled trees
+        for dname in ("f32", "bf16", "f64"):
+            rows += tune_batch("compiled", DT_NAMES[dname], serving_scenarios(), with_dot=False,
+                               reps=args.reps, verbose=True)
     if args.merge and os.path.exists(args.out):
         rows = merged(read_table(args.out), rows)
     write_table(rows, args.out)
