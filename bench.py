@@ -29,6 +29,8 @@ step):
     precision: dot / nrm2 at n = 2^26, storage FP64 / FP32 / BF16, with the
                error against the binary64 oracle per result;
     blas1:     asum, iamax, scal and the strided routines at increments 2, 4;
+    vendor:    rocBLAS axpy, dot, nrm2, copy, scal at n = 2^28 (binary64,
+               binary32) beside the library's, on the same buffers and stream;
     batched:   4096 lognormal-length instances of alpha*a + (b - c) plus
                dot(a, b) in one persistent launch replayed from a HIP graph,
                against 4096 separate launches and one binary64 kernel;
@@ -40,7 +42,7 @@ step):
                on sampled elements (served_parity_ok).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
-                    [--sections main,mix,sweep,fusion,precision,blas1,batched,served]
+                    [--sections main,mix,sweep,fusion,precision,blas1,vendor,batched,served]
 """
 from __future__ import annotations
 
@@ -427,6 +429,82 @@ def section_sweep(args):
                          "rows": v} for k, v in rows.items()}
         del a, b, c, e, f, d, ws
         torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the vendor BLAS on the same GPU (context: the paper compares with BLAS)
+# ---------------------------------------------------------------------------
+
+def section_vendor(args):
+    """rocBLAS level-1 routines (axpy, dot, nrm2, copy, scal) at n = 2^28 in
+    binary64 and binary32, beside the library's own on the same buffers,
+    both timed with HIP events on the same stream (the paper's comparison
+    is against CPU BLAS, Sec. 5; this is the GPU's vendor BLAS). Results
+    are not compared: rocBLAS's summation order is its own."""
+    import ctypes
+
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+
+    try:
+        rb = ctypes.CDLL("librocblas.so")
+    except OSError as e:
+        return {"available": False, "why": str(e)}
+    h = ctypes.c_void_p()
+    if rb.rocblas_create_handle(ctypes.byref(h)) != 0:
+        return {"available": False, "why": "rocblas_create_handle failed"}
+    n = 1 << args.log2n
+    log("bench: rocBLAS level-1 beside the library, n = 2^%d" % args.log2n)
+    P = ctypes.c_void_p
+    out = {"available": True, "n": n,
+           "columns": ["rocblas_ms", "rocblas_GBps", "library_ms", "library_GBps", "library_over_rocblas"]}
+    cat = dict(salt.salt_catalogue())
+    try:
+        if rb.rocblas_set_stream(h, P(torch.cuda.current_stream().cuda_stream)) != 0:
+            return {"available": False, "why": "rocblas_set_stream failed"}
+        for dt, code, es, pre, cty in (("f64", salt.F64, 8, "d", ctypes.c_double),
+                                       ("f32", salt.F32, 4, "s", ctypes.c_float)):
+            x, y = workloads.uniform_device(n, dt, workloads.sweep_seed(n) + 9, 2)
+            res = torch.empty(1, dtype=x.dtype, device="cuda")
+            ws = salt.workspace(n, code)
+            alpha = cty(1.25)
+            f = {k: getattr(rb, "rocblas_%s%s" % (pre, k)) for k in ("axpy", "dot", "nrm2", "copy", "scal")}
+            px, py, pr = P(x.data_ptr()), P(y.data_ptr()), P(res.data_ptr())
+
+            def call(st):
+                if st != 0:
+                    raise RuntimeError("rocBLAS status %d" % st)
+
+            vendor = {
+                "axpy": lambda: (rb.rocblas_set_pointer_mode(h, 0),
+                                 call(f["axpy"](h, ctypes.c_int(n), ctypes.byref(alpha), px, 1, py, 1))),
+                "dot": lambda: (rb.rocblas_set_pointer_mode(h, 1), call(f["dot"](h, ctypes.c_int(n), px, 1, py, 1, pr))),
+                "nrm2": lambda: (rb.rocblas_set_pointer_mode(h, 1), call(f["nrm2"](h, ctypes.c_int(n), px, 1, pr))),
+                "copy": lambda: call(f["copy"](h, ctypes.c_int(n), px, 1, py, 1)),
+                "scal": lambda: (rb.rocblas_set_pointer_mode(h, 0),
+                                 call(f["scal"](h, ctypes.c_int(n), ctypes.byref(alpha), py, 1))),
+            }
+            ours = {"axpy": lambda: salt.salt_axpy(1.25, x, y),
+                    "dot": lambda: salt.salt_dot(x, y, result=res, ws=ws),
+                    "nrm2": lambda: salt.salt_nrm2(x, result=res, ws=ws),
+                    "copy": lambda: salt.salt_eval(cat["copy"], [x], [], y),
+                    "scal": lambda: salt.salt_scal(1.25, y, n)}
+            nbytes = {"axpy": 3, "dot": 2, "nrm2": 1, "copy": 2, "scal": 2}
+            rows = {}
+            for k in ours:
+                t_v = event_ms(vendor[k], 10)
+                t_o = event_ms(ours[k], 10)
+                b = nbytes[k] * es * n
+                rows[k] = [round(t_v, 4), round(b / (t_v * 1e-3) / 1e9, 1), round(t_o, 4),
+                           round(b / (t_o * 1e-3) / 1e9, 1), round(t_v / t_o, 3)]
+            out[dt] = rows
+            del x, y, ws
+            torch.cuda.empty_cache()
+    finally:
+        rb.rocblas_destroy_handle(h)
     return out
 
 
@@ -1192,7 +1270,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--sections", default="main,mix,sweep,fusion,precision,blas1,batched,served")
+    ap.add_argument("--sections", default="main,mix,sweep,fusion,precision,blas1,vendor,batched,served")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-log2n", type=int, default=26)
@@ -1244,6 +1322,8 @@ def main() -> int:
         out["precision"] = section_precision(args)
     if "blas1" in sections:
         out["blas1"] = section_blas1(args)
+    if "vendor" in sections:
+        out["vendor_blas"] = section_vendor(args)
     if "batched" in sections:
         out["batched"] = section_batched(args)
     if "served" in sections:
