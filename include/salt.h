@@ -506,6 +506,17 @@ salt_status salt_jit_code_reduce(const uint32_t *prog_x, int32_t len_x,
                                  int32_t n_operands, int32_t n_scalars, salt_dtype dtype,
                                  void *buf, size_t cap, size_t *size);
 
+/* How salt_eval launches a call of n elements of a tree that reads n_loads
+ * distinct operands (no GPU work): a tree reading three or more operands,
+ * over at least two chunks of 128 MiB per operand, runs as a sequence of
+ * launches over contiguous chunks (the last one taking the remainder, so
+ * between one and two chunks), each with the launch knobs tuned for its
+ * own size; otherwise one launch. *chunk_elems gets the elements per
+ * launch (n when not split), *launches the number of launches (0 for
+ * n = 0). The results are the same either way. */
+salt_status salt_eval_chunking(int32_t n_loads, int64_t n, salt_dtype dtype, int64_t *chunk_elems,
+                               int64_t *launches);
+
 /* Validate a program without touching the GPU. On success fills
  * *stack_need (maximum stack depth) and *n_loads (distinct operands read)
  * when those pointers are non-null. */

@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
         "salt_program_route": ([U32P, I32, I32, I32, ctypes.POINTER(I32)], I32),
         "salt_reduce_expr_route": ([U32P, I32, U32P, I32, I32, I32, I32, ctypes.POINTER(I32)], I32),
         "salt_jit_compile_reduce": ([U32P, I32, U32P, I32, I32, I32, I32], I32),
+        "salt_eval_chunking": ([I32, I64, I32, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "salt_jit_code_reduce": ([U32P, I32, U32P, I32, I32, I32, I32, P, SZ, ctypes.POINTER(SZ)], I32),
         "salt_jit_set_mode": ([I32], I32),
         "salt_jit_compile": ([U32P, I32, I32, I32, I32], I32),
@@ -564,6 +565,13 @@ def salt_jit_code(prog: Sequence[int], n_operands: int, n_scalars: int, dtype: i
     buf = ctypes.create_string_buffer(max(1, size.value))
     check(lib().salt_jit_code(arr, n, n_operands, n_scalars, dtype, buf, size.value, ctypes.byref(size)))
     return buf.raw[:size.value]
+
+
+def salt_eval_chunking(n_loads: int, n: int, dtype: int) -> tuple[int, int]:
+    """(elements per launch, launches) of an element-wise call."""
+    c, k = ctypes.c_int64(), ctypes.c_int64()
+    check(lib().salt_eval_chunking(n_loads, n, dtype, ctypes.byref(c), ctypes.byref(k)))
+    return c.value, k.value
 
 
 def salt_eval_route(prog: Sequence[int], n_operands: int, n_scalars: int, dtype: int) -> int:

@@ -329,3 +329,21 @@ def test_reduce_expr_route_matches_the_pair_catalogue():
     assert r([T(S.SCALAR, 0), L0, MUL, L0, ADD], None, 2, 1) == -1  # one operand twice
     with pytest.raises(S.SaltError):
         r([L0, L1, ADD], [L0, L2, SUB], 2, 0)                     # operand out of range
+
+
+def test_eval_chunking_policy():
+    """Large calls of trees reading three or more operands run as launches of
+    128 MiB per operand (the last takes the remainder); others as one."""
+    c64 = (128 << 20) // 8
+    assert S.salt_eval_chunking(5, 1 << 28, S.F64) == (c64, 16)
+    assert S.salt_eval_chunking(5, 2 * c64 - 1, S.F64) == (2 * c64 - 1, 1)   # below two chunks
+    assert S.salt_eval_chunking(3, 2 * c64, S.F64) == (c64, 2)
+    assert S.salt_eval_chunking(3, 3 * c64 - 1, S.F64) == (c64, 2)           # remainder in the last
+    assert S.salt_eval_chunking(2, 1 << 28, S.F64) == (1 << 28, 1)           # axpy-like: one launch
+    assert S.salt_eval_chunking(1, 1 << 28, S.F64) == (1 << 28, 1)
+    assert S.salt_eval_chunking(5, 1 << 28, S.BF16) == ((128 << 20) // 2, 4)
+    assert S.salt_eval_chunking(6, 0, S.F32) == (0, 0)
+    with pytest.raises(S.SaltError):
+        S.salt_eval_chunking(9, 10, S.F32)
+    with pytest.raises(S.SaltError):
+        S.salt_eval_chunking(3, -1, S.F32)
