@@ -407,6 +407,11 @@ typedef struct {
                               * blocks -1: tuned), or NULL: all tuned, per
                               * launch by its tree, type and size; unroll
                               * 2, 4 or 8 (a mixed-tree launch runs 8 as 4) */
+    int64_t range_bytes;     /* a group whose tiles hold more than twice this
+                              * many bytes per operand runs as several
+                              * launches over consecutive ranges of its tile
+                              * list, each with the knobs of its size (same
+                              * results); 0: 256 MiB, negative: never split */
 } salt_server_config;
 #define SALT_SERVE_SPLIT_ELEMS ((int64_t)1 << 26)
 

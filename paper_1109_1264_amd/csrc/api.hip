@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "batch_ranges.hpp"
 #include "blas1.hpp"
 #include "expr.hpp"
 #include "jit.hpp"
@@ -500,8 +501,23 @@ salt_status batch_launch_impl(salt_batch_plan plan, void *ws, size_t ws_bytes, v
     L.nontemporal = c.nontemporal;
     L.blocks = c.blocks;
     L.stream = stream;
-    if (plan->route == kRouteJit) return device_status(jit_batch_launch(L, plan->prog, plan->dtype));
-    return device_status((hipError_t)fn(L));
+    L.combine = 1;
+    // a long execution list runs as several launches over consecutive ranges
+    // (batch_ranges.hpp), each with the knobs tuned for its size
+    const auto knobs = [&](int64_t elems, BatchLaunch &r) -> int {
+        salt_launch_config k;
+        if (resolve(cfg, lookup(kBatch, plan->route, plan->dtype, elems, 4), kBatch, &k) != SALT_OK)
+            return (int)hipErrorInvalidValue;
+        r.unroll = k.unroll;
+        r.nontemporal = k.nontemporal;
+        r.blocks = k.blocks;
+        return 0;
+    };
+    const auto launch = [&](const BatchLaunch &r) -> int {
+        return plan->route == kRouteJit ? (int)jit_batch_launch(r, plan->prog, plan->dtype) : fn(r);
+    };
+    return device_status((hipError_t)launch_batch_ranges(launch, L, plan->total_elems, reduce_tile_elems(plan->dtype),
+                                                         (int64_t)esize(plan->dtype), knobs));
 }
 
 int canon_pair(const uint32_t *a, int32_t la, const uint32_t *b, int32_t lb, uint32_t *ca, uint32_t *cb,

@@ -39,8 +39,8 @@ void order_tiles(TileRef *refs, int64_t count, const DevItem *items, int64_t til
 // Host-side launch of the batched kernels for one (tree, dtype).
 struct BatchLaunch {
     const DevItem *items;
-    const TileRef *tiles;  // execution list
-    int64_t total_tiles;
+    const TileRef *tiles;  // execution list (or a consecutive range of it)
+    int64_t total_tiles;   // entries of `tiles` this launch runs
     int32_t count;
     int32_t any_dot;
     double *ws;  // one binary64 partial per global tile (when any_dot)
@@ -48,6 +48,8 @@ struct BatchLaunch {
     int32_t nontemporal;
     int64_t blocks;
     void *stream;
+    int32_t combine;  // when any_dot: run the per-item combine after the kernel
+                      // (0 for every range of a split list but the last)
 };
 
 using BatchFn = int (*)(const BatchLaunch &);  // returns a hipError_t

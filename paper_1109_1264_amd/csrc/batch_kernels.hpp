@@ -25,7 +25,7 @@ static int launch_batch_u(const BatchLaunch &L) {
         hipLaunchKernelGGL((k_batch<E, DT, UR, NT, DOT>), dim3((unsigned)grid), dim3(kBlock), 0,
                            (hipStream_t)L.stream, L.items, L.tiles, L.total_tiles, L.ws);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !DOT) return (int)e;
+    if (e != hipSuccess || !DOT || !L.combine) return (int)e;
     return launch_combine<DT>(L);
 }
 

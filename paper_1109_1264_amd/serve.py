@@ -32,7 +32,7 @@ class ServerConfig(ctypes.Structure):
                 ("max_inflight", ctypes.c_int32), ("n_streams", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("release_on_complete", ctypes.c_int32), ("grouping", ctypes.c_int32),
-                ("launch", ctypes.POINTER(S.LaunchConfig))]
+                ("launch", ctypes.POINTER(S.LaunchConfig)), ("range_bytes", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):
@@ -164,13 +164,15 @@ GROUP_MIXED, GROUP_BY_TREE, GROUP_AUTO = 0, 1, 2
 
 
 def serve(trace, arena, table, max_inflight=4096, n_streams=4, max_batch=512, depth=2, keep_outputs=False,
-          grouping=GROUP_MIXED, launch=None):
+          grouping=GROUP_MIXED, launch=None, range_bytes=0):
     """Run the trace through the native loop; returns the results array.
     Per element type a batch runs one mixed-tree launch (GROUP_MIXED), one
     single-tree launch per tree (GROUP_BY_TREE), or the latter only when the
     type's requests hold at least 2^26 elements (GROUP_AUTO). ``launch``:
     (unroll, nontemporal, blocks) for every batched launch (0 / -1 / -1
-    keep the tuned value), or None: tuned."""
+    keep the tuned value), or None: tuned. ``range_bytes``: bytes per
+    operand of one launch of a long tile list (0: the library's 256 MiB,
+    -1: never split)."""
     L = _declare()
     count = len(trace)
     res = (RequestResult * max(1, count))()
@@ -178,7 +180,7 @@ def serve(trace, arena, table, max_inflight=4096, n_streams=4, max_batch=512, de
     cfg = ServerConfig(arena.data_ptr(), arena.numel() * arena.element_size(), table.data_ptr(),
                        table.numel() * table.element_size(), max_inflight, n_streams, max_batch, depth,
                        0 if keep_outputs else 1, grouping,
-                       ctypes.pointer(knobs) if knobs is not None else None)
+                       ctypes.pointer(knobs) if knobs is not None else None, range_bytes)
     S.check(L.salt_serve_trace(ctypes.byref(cfg), trace, count, res))
     return res
 

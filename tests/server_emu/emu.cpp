@@ -4,10 +4,12 @@
 // at random moments (so completions interleave differently for each seed); a
 // table copy happens when the copy runs; a batched "launch" checks, when it
 // runs, that its descriptor table still holds what the host staged at launch
-// time, that its (item, tile) list is a permutation of the items' tiles, and
-// that every element range a tile touches lies inside the operand pool and
-// the output arena; at launch, no output may overlap the output of a batch
-// the host has not yet seen complete.
+// time, that its (item, tile) list is a permutation of the items' tiles (a
+// list split into consecutive launches is checked as a whole: every tile
+// once, and the group complete by the end of the run), and that every
+// element range a tile touches lies inside the operand pool and the output
+// arena; at launch, no output may overlap the output of a batch the host has
+// not yet seen complete.
 #include <hip/hip_runtime.h>
 
 #include <cassert>
@@ -66,6 +68,10 @@ struct Op {
 struct Stream {
     std::vector<Op> q;  // pending
     long next_seq = 1, done_seq = 0;
+    // the last kernel enqueued: its sequence number and item table (the
+    // ranges of one split list are enqueued back to back, sharing it)
+    long last_kernel_seq = -1;
+    const void *last_group = nullptr;
 };
 struct Event {
     Stream *s = nullptr;
@@ -76,11 +82,17 @@ static std::vector<Stream *> streams;
 struct Live {
     Range r;
     Stream *s;
-    long seq;
+    long seq;  // the last launch that writes it
 };
 static std::vector<Live> live;  // outputs of kernels the host has not yet seen complete
 
 static int g_tree = -1, g_dtype = -1;
+
+// Tiles run so far of each group whose list is split over several launches,
+// keyed by the group's item table; a group leaves the map when its list is
+// complete.
+static std::map<const void *, std::set<std::pair<int, int>>> group_seen;
+static long launches = 0, split_launches = 0;
 
 static int64_t T_of(int d) { return d == SALT_F64 ? 8192 : d == SALT_F32 ? 16384 : 32768; }
 static uint64_t es_of(int d) { return d == SALT_F64 ? 8 : d == SALT_F32 ? 4 : 2; }
@@ -102,10 +114,11 @@ static void exec_kernel(Op &op) {
     const salt::TileRef *tiles = (const salt::TileRef *)tiles_p;
     const int64_t T = T_of(op.dtype);
     const uint64_t es = es_of(op.dtype);
-    std::set<std::pair<int, int>> seen;
     int64_t want_tiles = 0;
     for (int k = 0; k < L.count; ++k) want_tiles += (items[k].n + T - 1) / T;
-    if (want_tiles != L.total_tiles) ERR("total tiles %ld vs %ld", (long)L.total_tiles, (long)want_tiles);
+    std::set<std::pair<int, int>> &seen = group_seen[items_p];
+    ++launches;
+    if (L.total_tiles != want_tiles || !seen.empty()) ++split_launches;
     for (int64_t g = 0; g < L.total_tiles; ++g) {
         const salt::TileRef r = tiles[g];
         if (r.item < 0 || r.item >= L.count) {
@@ -131,6 +144,8 @@ static void exec_kernel(Op &op) {
         const uint64_t a = (uint64_t)it.out + lo * es, b = (uint64_t)it.out + hi * es;
         if (!it.out || a < arena_lo || b > arena_hi) ERR("output outside arena");
     }
+    if ((int64_t)seen.size() > want_tiles) ERR("more tiles run than the group has");
+    if ((int64_t)seen.size() == want_tiles) group_seen.erase(items_p);  // the group's list is complete
 }
 
 static void step(Stream *s) {
@@ -254,9 +269,13 @@ void order_tiles(TileRef *refs, int64_t count, const DevItem *items, int64_t til
 }
 static int stub_launch(const BatchLaunch &L) {
     Stream *st = (Stream *)L.stream;
+    // a further range of the list the previous launch on this stream began
+    const bool cont = st->last_group == (const void *)L.items && st->last_kernel_seq == st->next_seq - 1;
     Op op;
     op.kind = 1;
     op.seq = st->next_seq++;
+    st->last_kernel_seq = op.seq;
+    st->last_group = (const void *)L.items;
     op.L = L;
     op.tree = g_tree;
     op.dtype = g_dtype;
@@ -276,13 +295,20 @@ static int stub_launch(const BatchLaunch &L) {
         op.expect_tiles.assign(src_tiles, src_tiles + sizeof(TileRef) * L.total_tiles);
         const DevItem *items = (const DevItem *)src_items;
         const uint64_t es = es_of(g_dtype);
-        for (int k = 0; k < L.count; ++k) {
-            Range r{(uint64_t)items[k].out, (uint64_t)items[k].out + (uint64_t)items[k].n * es};
-            for (auto &lv : live)
-                if (r.lo < lv.r.hi && lv.r.lo < r.hi) ERR("output overlaps a live output of another batch");
-            op.outs.push_back(r);
+        // the outputs are checked and made live by a list's first launch; its
+        // further ranges write the same outputs
+        if (!cont) {
+            for (int k = 0; k < L.count; ++k) {
+                Range r{(uint64_t)items[k].out, (uint64_t)items[k].out + (uint64_t)items[k].n * es};
+                for (auto &lv : live)
+                    if (r.lo < lv.r.hi && lv.r.lo < r.hi) ERR("output overlaps a live output of another batch");
+                op.outs.push_back(r);
+            }
+            for (auto &r : op.outs) live.push_back({r, st, op.seq});
+        } else {
+            for (auto &lv : live)  // keep the list's outputs live until its last range completes
+                if (lv.s == st && lv.seq == op.seq - 1) lv.seq = op.seq;
         }
-        for (auto &r : op.outs) live.push_back({r, st, op.seq});
     }
     st->q.push_back(op);
     return 0;
@@ -300,9 +326,9 @@ BatchFn catalogue_batch_multi_launcher(int dtype) {
 }  // namespace salt
 
 int main(int argc, char **argv) {
-    if (argc != 9 && argc != 10) {
-        std::fprintf(stderr,
-                     "usage: emu pool.txt trace.bin arena_gb p_step seed max_batch n_streams depth [grouping]\n");
+    if (argc < 9 || argc > 11) {
+        std::fprintf(stderr, "usage: emu pool.txt trace.bin arena_gb p_step seed max_batch n_streams depth "
+                             "[grouping [range_bytes]]\n");
         return 2;
     }
     FILE *f = std::fopen(argv[1], "r");
@@ -339,13 +365,15 @@ int main(int argc, char **argv) {
     cfg.max_batch = max_batch;
     cfg.depth = depth;
     cfg.release_on_complete = 1;
-    cfg.grouping = argc == 10 ? std::atoi(argv[9]) : 0;
+    cfg.grouping = argc >= 10 ? std::atoi(argv[9]) : 0;
+    cfg.range_bytes = argc >= 11 ? std::atoll(argv[10]) : 0;
     std::vector<salt_request_result> res(reqs.size());
     std::string err;
     const salt_status s = salt::serve_trace_impl(&cfg, reqs.data(), (int32_t)reqs.size(), res.data(), &err);
     int rejected = 0;
     for (auto &x : res) rejected += x.status != SALT_OK;
-    std::printf("%s: status %d (%s), %zu requests, %d rejected, errors %ld\n", argv[2], (int)s, err.c_str(),
-                reqs.size(), rejected, n_errors);
+    if (!group_seen.empty()) ERR("%zu groups with tiles never run", group_seen.size());
+    std::printf("%s: status %d (%s), %zu requests, %d rejected, %ld launches (%ld of split lists), errors %ld\n",
+                argv[2], (int)s, err.c_str(), reqs.size(), rejected, launches, split_launches, n_errors);
     return n_errors ? 1 : (s != SALT_OK ? 3 : 0);
 }

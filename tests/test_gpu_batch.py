@@ -289,3 +289,35 @@ def test_compiled_tree_batch_launch_shapes():
                     if ref_dot[i] is not None:
                         assert float(it["dot_out"].item()) == ref_dot[i], (unroll, nt, blocks, i)
     b.close()
+
+
+def test_long_list_split_into_ranges():
+    """A plan whose tiles hold more than twice 128 MiB per operand runs as
+    several launches over consecutive ranges of its list, the dots' combine
+    after the last: outputs bit-exact against the oracle, every dot with the
+    bits of salt_dot alone, the same bits from a graph of the plan."""
+    import torch
+
+    dtype = "bf16"
+    lengths = [(1 << 24) + 17 * i for i in range(9)] + [5, 70000]   # 288 MiB per operand: two ranges
+    items, host = make_batch(dtype, lengths, 3300, dot_every=2)
+    b = Batch(ABC, items, CODE[dtype])
+    print("long batch", b.tiles, "tiles", flush=True)
+    b.launch()
+    check(items, host, dtype)
+    ref_out = [to_host_bits(it["out"], dtype) for it in items]
+    ref_dot = [None if it["dot_out"] is None else float(it["dot_out"].item()) for it in items]
+    g = b.graph()
+    for it in items:
+        it["out"].zero_()
+        if it["dot_out"] is not None:
+            it["dot_out"].fill_(-1.0)
+    torch.cuda.synchronize()
+    g.launch()
+    torch.cuda.synchronize()
+    for i, it in enumerate(items):
+        assert np.array_equal(to_host_bits(it["out"], dtype), ref_out[i]), i
+        if ref_dot[i] is not None:
+            assert float(it["dot_out"].item()) == ref_dot[i], i
+    g.close()
+    b.close()

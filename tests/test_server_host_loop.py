@@ -4,7 +4,8 @@ The loop is compiled for the host only and linked with an emulation of its
 device side (``tests/server_emu/emu.cpp``): streams run their queued copies,
 launches and event records in order at random moments, so every seed gives a
 different interleaving of completions. Each emulated launch checks its
-descriptor table, its (item, tile) list and every element range its tiles
+descriptor table, its (item, tile) list (as a whole when the loop splits a
+long list over several launches) and every element range its tiles
 touch against the operand pool and the output arena, and that no output
 overlaps the output of a batch the host has not yet seen complete. Traces are
 the served benchmark's (same generator and seeds) with addresses of a pool
@@ -81,10 +82,10 @@ def setup(tmp_path_factory):
     return tmp, build(tmp, os.path.join(CSRC, "server.hip")), traces
 
 
-def run(exe, tmp, trace, arena_gb, p, seed, max_batch=512, streams=4, depth=2, grouping=0):
+def run(exe, tmp, trace, arena_gb, p, seed, max_batch=512, streams=4, depth=2, grouping=0, range_bytes=0):
     return subprocess.run([exe, os.path.join(tmp, "pool.txt"), trace, str(arena_gb), str(p), str(seed),
-                           str(max_batch), str(streams), str(depth), str(grouping)], capture_output=True, text=True,
-                          timeout=300)
+                           str(max_batch), str(streams), str(depth), str(grouping), str(range_bytes)],
+                          capture_output=True, text=True, timeout=300)
 
 
 @pytest.mark.parametrize("grouping", [0, 1, 2])
@@ -95,6 +96,19 @@ def test_loop_tables_tiles_and_addresses(setup, trace, grouping):
                                           (4, 0.02, 4, 2048, 2, 1)):
         r = run(exe, tmp, traces[trace], arena_gb, p, seed, mb, ns, dp, grouping)
         assert r.returncode == 0, (trace, arena_gb, p, seed, r.stdout, r.stderr[-2000:])
+
+
+@pytest.mark.parametrize("range_bytes", [16 << 20, 64 << 20, -1])
+def test_split_tile_lists(setup, range_bytes):
+    """Long tile lists run as consecutive ranges (down to 16 MiB per operand,
+    so most large groups split): every tile of every group runs exactly
+    once, all groups complete, and the other checks hold; -1 never splits."""
+    tmp, exe, traces = setup
+    for trace, seed in (("saturation", 5), ("poisson", 6)):
+        r = run(exe, tmp, traces[trace], 32, 0.3, seed, 512, 4, 2, 0, range_bytes)
+        assert r.returncode == 0, (trace, range_bytes, r.stdout, r.stderr[-2000:])
+        split = int(r.stdout.split("launches (")[1].split(" of split")[0])
+        assert (split > 0) == (range_bytes > 0), r.stdout
 
 
 def test_planted_early_release_is_caught(setup, tmp_path):
