@@ -7,7 +7,8 @@
 // Splitting the list into ranges of about kBatchRangeBytes per operand, each
 // its own launch with the knobs tuned for its size, restarts the grid in
 // step at every range (measured 5-16 % faster on groups of 2 GiB per
-// operand). Every tile still runs exactly once and writes its own outputs
+// operand; a list under two ranges' worth of elements stays one launch,
+// where the extra launch would cost more than the drift). Every tile still runs exactly once and writes its own outputs
 // and partial, so the results do not depend on the split; the per-item
 // combine of the dots runs once, after the last range.
 #pragma once
@@ -22,11 +23,14 @@ constexpr int64_t kBatchRangeBytes = (int64_t)128 << 20;
 
 // Tiles per range for tiles of tile_elems elements of es bytes, ranges of
 // range_bytes per operand (0: kBatchRangeBytes; negative: never split), or
-// 0 when a list of total_tiles tiles runs as one launch.
-inline int64_t batch_range_tiles(int64_t total_tiles, int64_t tile_elems, int64_t es, int64_t range_bytes = 0) {
+// 0 when the list runs as one launch: its items hold total_elems elements,
+// fewer than two ranges' worth (the decision counts elements, not tiles,
+// since a list of many short items has many partly filled tiles).
+inline int64_t batch_range_tiles(int64_t total_elems, int64_t tile_elems, int64_t es, int64_t range_bytes = 0) {
     if (range_bytes < 0) return 0;
-    const int64_t per = (range_bytes > 0 ? range_bytes : kBatchRangeBytes) / (tile_elems * es);
-    return per > 0 && total_tiles >= 2 * per ? per : 0;
+    const int64_t bytes = range_bytes > 0 ? range_bytes : kBatchRangeBytes;
+    const int64_t per = bytes / (tile_elems * es);
+    return per > 0 && total_elems * es >= 2 * bytes ? per : 0;
 }
 
 // Launch L's list (its items holding total_elems elements) as ranges with
@@ -37,8 +41,8 @@ inline int64_t batch_range_tiles(int64_t total_tiles, int64_t tile_elems, int64_
 template <class Launch, class Knobs>
 int launch_batch_ranges(const Launch &fn, const BatchLaunch &L, int64_t total_elems, int64_t tile_elems,
                         int64_t es, const Knobs &knobs, int64_t range_bytes = 0) {
-    const int64_t per = batch_range_tiles(L.total_tiles, tile_elems, es, range_bytes);
-    if (per == 0) {
+    const int64_t per = batch_range_tiles(total_elems, tile_elems, es, range_bytes);
+    if (per == 0 || L.total_tiles < 2 * per) {
         BatchLaunch one = L;
         one.combine = 1;
         const int st = knobs(total_elems, one);
