@@ -262,7 +262,7 @@ salt_status eval_impl(const uint32_t *prog, int32_t prog_len, const void *const 
     if (p.n_loads > 0 && !operands) return fail(SALT_ERR_ARG, "operand array is NULL");
     if (p.n_scal > 0 && !scalars) return fail(SALT_ERR_ARG, "scalar array is NULL");
     const int route = route_of(p);
-    salt_launch_config c;
+    salt_launch_config c;  // checks the caller's knobs before anything runs (each launch resolves its own)
     s = resolve(cfg, lookup(kEval, route, dtype, n, p.n_loads + 1), kEval, &c);
     if (s != SALT_OK) return s;
     if (n == 0) return SALT_OK;
