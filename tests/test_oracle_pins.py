@@ -600,7 +600,34 @@ def check_iamax(o):
     assert o.iamax(3, hf, 1, "f16") == 1
 
 
+def check_h16_double_rounding(o):
+    """The last operation of a 16-bit tree is rounded to binary32, then the
+    result narrowed once (two roundings), not rounded from the exact value
+    straight to 16 bits: a scalar multiple chosen so that the two differ on
+    many inputs, against numpy (binary16) and torch (bfloat16) conversions
+    of the binary32 products."""
+    import torch
+
+    alpha = 1.9255319833755493
+    a32 = np.float32(alpha)
+    x = np.arange(0x0400, 0x7800, dtype=np.uint16)             # positive binary16 normals below 2^15
+    xf = x.view(np.float16).astype(np.float32)
+    prog = [tok(SCALAR, 0), tok(LOAD, 0), tok(MUL)]
+    exact = xf.astype(np.float64) * float(a32)
+    twice = (xf * a32).astype(np.float16)
+    assert np.count_nonzero(exact.astype(np.float16) != twice) >= 50    # one rounding differs here
+    got = o.eval_program(prog, [x], [alpha], "f16")
+    assert np.array_equal(np.asarray(got).view(np.uint16), twice.view(np.uint16))
+    # bfloat16: all bfloat16 values in [0.5, 2), the binary32 product rounded by torch
+    xb = np.arange(0x3f00, 0x4000, dtype=np.uint16)
+    xbf = torch.from_numpy(xb.view(np.int16)).view(torch.bfloat16).to(torch.float32)
+    want = (xbf * torch.tensor(a32)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    got = o.eval_program(prog, [xb], [alpha], "bf16")
+    assert np.array_equal(np.asarray(got).view(np.uint16), want)
+
+
 CHECKS = {
+    "h16_double_rounding": check_h16_double_rounding,
     "fig1_golden": check_fig1_golden,
     "python_float_trees_f64": check_python_float_trees_f64,
     "random_programs_f64": lambda o: check_random_programs(o, "f64"),
