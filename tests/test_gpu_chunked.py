@@ -86,3 +86,34 @@ def test_tree_outside_the_catalogue(mode):
     finally:
         S.salt_jit_set_mode(S.JIT_AUTO)
     assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+def test_chunked_call_in_a_graph():
+    """A chunked call captured into a HIP graph replays the same bits, with
+    eager work and synchronisations between the replays."""
+    import torch
+
+    dtype = "f64"
+    n = length(dtype, extra=3)
+    fig1 = dict(S.salt_catalogue())["fig1"]
+    assert S.salt_eval_chunking(3, n, S.F64)[1] == 2
+    host = workloads.uniform(n, dtype, 9400, 3)
+    dev = [to_dev(h, dtype) for h in host]
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    S.salt_eval(fig1, dev, [], out)                  # eager first (loads nothing new, sets the tuned path)
+    torch.cuda.synchronize()
+    want = out.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        S.salt_eval(fig1, dev, [], out)
+    for rep in range(3):
+        out.zero_()
+        torch.randn(1 << 20, device="cuda").mul_(3.0).sum()     # unrelated eager work
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(torch.int64), want.view(torch.int64)), rep
+    del g
+    got = out.cpu().numpy().view(np.uint64)
+    ref = oracle_bits(oracle.eval_program(fig1, host, [], dtype), dtype)
+    assert np.array_equal(got, ref), first_mismatch(got, ref)
