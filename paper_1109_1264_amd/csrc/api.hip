@@ -748,16 +748,20 @@ salt_status tuned_config(int kind, int route, int dtype, int64_t n, salt_launch_
     return SALT_OK;
 }
 
-// Validate the programs of a dot (prog_y non-null) or nrm2 of expressions.
+// Validate the programs of a dot (prog_y non-null) or nrm2 of expressions,
+// with the rule the reduction applies: one of a dot's two programs must fit
+// in SALT_MAX_STACK - 1 slots.
 salt_status check_pair(const uint32_t *prog_x, int32_t len_x, const uint32_t *prog_y, int32_t len_y,
                        int32_t n_operands, int32_t n_scalars) {
-    Program p;
+    Program p, q;
     std::string why;
     salt_status s = compile_program(prog_x, len_x, n_operands, n_scalars, &p, &why);
     if (s != SALT_OK) return fail(s, "first program: " + why);
     if (prog_y) {
-        s = compile_program(prog_y, len_y, n_operands, n_scalars, &p, &why);
+        s = compile_program(prog_y, len_y, n_operands, n_scalars, &q, &why);
         if (s != SALT_OK) return fail(s, "second program: " + why);
+        if (p.stack_need > SALT_MAX_STACK - 1 && q.stack_need > SALT_MAX_STACK - 1)
+            return fail(SALT_ERR_UNSUPPORTED, "both programs need all 8 stack slots");
     }
     return SALT_OK;
 }
