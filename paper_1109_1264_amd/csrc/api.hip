@@ -8,12 +8,15 @@
 #include <dlfcn.h>
 
 #include <cerrno>
+#include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <unordered_map>
 #include <utility>
 #include <mutex>
 #include <string>
@@ -131,8 +134,37 @@ struct TuneRow {
     salt_launch_config cfg;
 };
 
+// The table by (kind, route, dtype): for every log2 size the row the
+// nearest-size rule picks (the first in file order among equally near
+// rows), so a lookup is one hash probe instead of a scan of the table.
+constexpr int kTuneSizes = 63;  // log2 n = 0 .. 62
+using TuneSizes = std::array<salt_launch_config, kTuneSizes>;
+
+uint64_t tune_key(int kind, int route, int dtype) {
+    return ((uint64_t)(uint32_t)kind << 40) | ((uint64_t)(uint32_t)route << 8) | (uint64_t)(uint8_t)dtype;
+}
+
+std::unordered_map<uint64_t, TuneSizes> index_tune(const std::vector<TuneRow> &rows) {
+    std::unordered_map<uint64_t, TuneSizes> ix;
+    std::unordered_map<uint64_t, std::array<int, kTuneSizes>> dist;
+    for (const TuneRow &r : rows) {
+        const uint64_t k = tune_key(r.kind, r.route, r.dtype);
+        auto d = dist.try_emplace(k);
+        if (d.second) d.first->second.fill(INT_MAX);
+        TuneSizes &cfgs = ix[k];
+        for (int l = 0; l < kTuneSizes; ++l) {
+            const int dl = std::abs(r.log2n - l);
+            if (dl < d.first->second[l]) {
+                d.first->second[l] = dl;
+                cfgs[l] = r.cfg;
+            }
+        }
+    }
+    return ix;
+}
+
 std::mutex g_tune_mu;
-std::vector<TuneRow> g_tune;
+std::unordered_map<uint64_t, TuneSizes> g_tune;  // the loaded table, indexed
 bool g_tune_loaded = false;
 
 std::string default_tune_path() {
@@ -188,14 +220,10 @@ void ensure_tune_loaded() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
     std::vector<TuneRow> rows;
-    if (parse_tune(default_tune_path(), rows, nullptr)) g_tune = rows;
+    if (parse_tune(default_tune_path(), rows, nullptr)) g_tune = index_tune(rows);
 }
 
-int ilog2(int64_t n) {
-    int l = 0;
-    while (n > 1) n >>= 1, ++l;
-    return l;
-}
+int ilog2(int64_t n) { return n > 1 ? 63 - __builtin_clzll((unsigned long long)n) : 0; }
 
 // Defaults before any measurement: 4 chunks per operand per lane, streaming
 // hints above the 256 MiB last-level cache, one workgroup per tile.
@@ -212,15 +240,9 @@ salt_launch_config default_cfg(int kind, int dtype, int64_t n, int n_arrays) {
 salt_launch_config lookup(int kind, int route, int dtype, int64_t n, int n_arrays) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     ensure_tune_loaded();
-    const int l = ilog2(n > 0 ? n : 1);
-    const TuneRow *best = nullptr;
-    int bestd = INT_MAX;
-    for (const auto &r : g_tune) {
-        if (r.kind != kind || r.route != route || r.dtype != dtype) continue;
-        const int d = std::abs(r.log2n - l);
-        if (d < bestd) bestd = d, best = &r;
-    }
-    return best ? best->cfg : default_cfg(kind, dtype, n, n_arrays);
+    const auto it = g_tune.find(tune_key(kind, route, dtype));
+    if (it == g_tune.end()) return default_cfg(kind, dtype, n, n_arrays);
+    return it->second[std::min(ilog2(n > 0 ? n : 1), kTuneSizes - 1)];
 }
 
 // Knobs of a call: the tuned values, overridden by the caller's. Unroll
@@ -1248,8 +1270,9 @@ salt_status salt_tuning_load(const char *path) {
     std::string why;
     const std::string p = path ? std::string(path) : default_tune_path();
     if (!parse_tune(p, rows, &why)) return fail(SALT_ERR_ARG, why);
+    auto ix = index_tune(rows);
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune = rows;
+    g_tune = std::move(ix);
     g_tune_loaded = true;
     return SALT_OK;
 }

@@ -208,6 +208,30 @@ def test_tuning_table(tmp_path):
             S.salt_tuning_load(str(empty))
 
 
+def test_tuning_lookup_is_the_nearest_row_of_the_packaged_table():
+    """Every (kind, route, dtype) of the packaged table at every log2 size:
+    the library's lookup returns the row nearest in log2 n, the first in
+    file order among equally near rows (a scan of the file, written out
+    here)."""
+    path = os.path.join(ROOT, "paper_1109_1264_amd", "salt_tuning.txt")
+    kinds = {"eval": 0, "dot": 1, "nrm2": 2, "batch": 3}
+    rows = []
+    for line in open(path):
+        f = line.split("#")[0].split()
+        if f:
+            rows.append((kinds[f[0]], int(f[1]), int(f[2]), int(f[3]), (int(f[4]), int(f[5]), int(f[6]))))
+    S.salt_tuning_load(None)
+    keys = sorted({r[:3] for r in rows})
+    assert len(keys) > 50
+    for kind, route, dt in keys:
+        mine = [r for r in rows if r[:3] == (kind, route, dt)]
+        for l in range(0, 60):
+            best = min(mine, key=lambda r: abs(r[3] - l))      # min keeps the first of equals
+            assert S.salt_tuning_lookup(kind, route, dt, 1 << l) == best[4], (kind, route, dt, l)
+        # sizes between powers of two use the floor of log2 n
+        assert S.salt_tuning_lookup(kind, route, dt, 3 << 20) == S.salt_tuning_lookup(kind, route, dt, 1 << 21)
+
+
 def test_reduce_expr_argument_errors(L):
     X, Y, R, W = 0x100000, 0x200000, 0x300000, 0x400000
     n = 100000
