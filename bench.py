@@ -81,12 +81,17 @@ def kernel_source_hash() -> str:
 
 def traffic_from_profile(n_elems: int):
     """HBM bytes per launch of the tree kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source and with
+    the library's current split of the call into dispatches."""
     if not os.path.exists(PROFILE_PMC):
         return None
     with open(PROFILE_PMC) as fh:
         d = json.load(fh)
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n") != n_elems:
+        return None
+    import paper_1109_1264_amd.salt as salt
+
+    if salt.salt_eval_chunking(5, n_elems, salt.F64)[1] != d.get("dispatches_per_launch"):
         return None
     return d.get("traffic_bytes_per_launch")
 

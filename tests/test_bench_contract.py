@@ -35,7 +35,7 @@ def test_cpu_baseline_record():
     json.dumps(rec)  # one JSON line
 
 
-def test_traffic_only_for_the_profiled_kernel_source():
+def test_traffic_only_for_the_profiled_kernel_source(tmp_path):
     """The counter-derived traffic is reported only while the committed
     counter summary was taken on the current tree-kernel source."""
     sys.path.insert(0, ROOT)
@@ -44,10 +44,24 @@ def test_traffic_only_for_the_profiled_kernel_source():
     with open(bench.PROFILE_PMC) as fh:
         prof = json.load(fh)
     got = bench.traffic_from_profile(prof["n"])
-    if prof["kernel_source_hash"] == bench.kernel_source_hash():
+    from paper_1109_1264_amd import salt as S
+
+    same_split = S.salt_eval_chunking(5, prof["n"], S.F64)[1] == prof["dispatches_per_launch"]
+    if prof["kernel_source_hash"] == bench.kernel_source_hash() and same_split:
         assert got == prof["traffic_bytes_per_launch"]
     else:
         assert got is None
+    # a record taken with another split of the call is not used
+    other = dict(prof, dispatches_per_launch=prof["dispatches_per_launch"] + 1)
+    alt = os.path.join(str(tmp_path), "pmc.json")
+    with open(alt, "w") as fh:
+        json.dump(other, fh)
+    saved = bench.PROFILE_PMC
+    bench.PROFILE_PMC = alt
+    try:
+        assert bench.traffic_from_profile(prof["n"]) is None
+    finally:
+        bench.PROFILE_PMC = saved
 
 
 def test_traffic_is_derived_from_request_counts():
