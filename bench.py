@@ -442,7 +442,50 @@ def section_sweep(args):
                          "rows": v} for k, v in rows.items()}
         del a, b, c, e, f, d, ws
         torch.cuda.empty_cache()
+    out["host_enqueue_us"] = host_enqueue_us()
     return out
+
+
+def host_enqueue_us(n: int = 1024, calls: int = 2000) -> dict:
+    """Host time per call to put one small call on the stream (the Python
+    binding, the library's checks and knob lookup, and the HIP launches),
+    with a torch element-wise op beside it; n binary64 elements, so the
+    device keeps up and the host is what is timed."""
+    import torch
+
+    import paper_1109_1264_amd.salt as salt
+    from paper_1109_1264_amd import workloads
+    from paper_1109_1264_amd.expr import Vec, expression
+
+    T = salt.token
+    tree5 = [T(salt.LOAD, 0), T(salt.LOAD, 1), T(salt.MUL), T(salt.LOAD, 2), T(salt.LOAD, 3), T(salt.MUL),
+             T(salt.ADD), T(salt.LOAD, 4), T(salt.SUB)]
+    v = workloads.uniform_device(n, "f64", 91, 5)
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    ws = salt.workspace(n, salt.F64)
+    r = torch.empty(1, dtype=torch.float64, device="cuda")
+    a, b, c, e, f = (Vec(t) for t in v)
+    dv = Vec(d)
+    t5 = expression(lambda a, b, c, e, f: a * b + c * e - f)
+    fns = {"salt_eval tree5": lambda: salt.salt_eval(tree5, v, [], d),
+           "operators d[:] = a*b + c*e - f (tree built per call)": lambda: dv.__setitem__(slice(None),
+                                                                                         a * b + c * e - f),
+           "expression(...) built once, called": lambda: t5(d, *v),
+           "salt_axpy": lambda: salt.salt_axpy(1.5, v[0], d),
+           "salt_dot (two kernels)": lambda: salt.salt_dot(v[0], v[1], result=r, ws=ws),
+           "torch.add (reference)": lambda: torch.add(v[0], v[1], out=d)}
+    res = {}
+    for k, fn in fns.items():
+        for _ in range(50):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            fn()
+        t1 = time.perf_counter()
+        torch.cuda.synchronize()
+        res[k] = round((t1 - t0) / calls * 1e6, 2)
+    return {"n": n, "dtype": "f64", "calls": calls, "us_per_call": res}
 
 
 # ---------------------------------------------------------------------------

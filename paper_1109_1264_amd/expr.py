@@ -21,13 +21,20 @@ has the operands of its additions and multiplications exchanged where that
 lowers the need (IEEE addition and multiplication are commutative, so every
 result keeps its bits); a subtraction keeps its order.
 
+Building the tree costs host time on every statement (tens of
+microseconds in Python). ``expression(fn)`` builds it once from a function
+of placeholder parameters, the counterpart of C++'s compile-time expression
+types; each call then costs one library call's marshalling.
+
 Example::
 
-    from paper_1109_1264_amd.expr import Vec, dot, norm
+    from paper_1109_1264_amd.expr import Vec, dot, expression, norm
     a, b, c, d = (Vec(t) for t in (ta, tb, tc, td))   # 1-D GPU tensors, one dtype
     d[:] = a + (b - c)            # Fig. 1: one kernel, one pass over memory
     d[:] = 2.5 * a + d            # axpy, in place
     r = dot(a + b, a - b)         # device scalar; a + b and a - b are never stored
+    fig1 = expression(lambda a, b, c: a + (b - c))
+    fig1(td, ta, tb, tc)          # the same call, tree built once
 """
 from __future__ import annotations
 
@@ -37,7 +44,8 @@ from typing import Sequence
 
 from . import salt as S
 
-__all__ = ["Expr", "Vec", "Scalar", "Node", "Program", "program", "pair_program", "stack_need", "dot", "norm"]
+__all__ = ["Expr", "Vec", "Scalar", "Param", "Node", "expression", "Program", "program", "pair_program", "operand_key", "stack_need",
+           "dot", "norm"]
 
 _SYMBOL = {S.ADD: "+", S.SUB: "-", S.MUL: "*"}
 
@@ -132,6 +140,19 @@ class Scalar(Expr):
         return repr(self.value)
 
 
+class Param(Expr):
+    """A leaf of a tree built once by `expression`: the vector or scalar
+    passed in that position of each call."""
+
+    __slots__ = ("slot", "scalar", "name")
+
+    def __init__(self, slot, scalar, name):
+        self.slot, self.scalar, self.name = slot, scalar, name
+
+    def __repr__(self):
+        return self.name
+
+
 class Node(Expr):
     """An operation: op in (ADD, SUB, MUL) applied to two subtrees."""
 
@@ -161,19 +182,6 @@ def _node(op, left, right):
         return NotImplemented
 
 
-def _count_nodes(roots: Sequence[Expr], limit: int) -> int:
-    """Tokens the trees expand to (a subtree used twice counts twice),
-    stopping once past `limit`."""
-    count, todo = 0, list(roots)
-    while todo and count <= limit:
-        e = todo.pop()
-        count += 1
-        if isinstance(e, Node):
-            todo.append(e.left)
-            todo.append(e.right)
-    return count
-
-
 def _need(e: Expr, swap: bool, memo: dict) -> int:
     """Stack slots the postfix of `e` needs (left operand first; with `swap`
     the larger side of an addition or multiplication goes first)."""
@@ -191,6 +199,12 @@ def _need(e: Expr, swap: bool, memo: dict) -> int:
     return v
 
 
+def operand_key(t):
+    """Vectors are one operand when they are the same memory: start, length,
+    element type and device."""
+    return (t.data_ptr(), t.numel(), t.dtype, t.get_device())
+
+
 class Program:
     """Trees over one shared list of operands and scalars, as the library's
     postfix programs: `tokens` for the first tree (and `tokens2` for a
@@ -200,64 +214,90 @@ class Program:
         self.operands = []   # torch tensors, LOAD k reads operands[k]
         self.scalars = []    # floats, SCALAR j reads scalars[j]
         self._ops = {}
+        self._keys = []      # operand_key of each operand
+        self._seen = {}      # id(tensor) -> operand index (tensors are held in operands)
         self._scs = {}
         self.tokens = []
         self.tokens2 = None
+        self.template = False  # built by expression(): leaves are Params and literals
+        self.params = 0        # scalar parameters ahead of the literals (expression())
 
     def _operand(self, v: Vec) -> int:
+        if self.template:
+            raise TypeError("a tree built by expression() takes its vectors as parameters, not %r" % (v,))
         t = v.tensor
-        key = (t.data_ptr(), t.numel(), t.dtype, str(t.device))
-        if key not in self._ops:
+        k = self._seen.get(id(t))
+        if k is not None:
+            return k
+        key = operand_key(t)
+        k = self._ops.get(key)
+        if k is None:
             if self.operands:
-                ref = self.operands[0]
-                if t.dtype != ref.dtype:
-                    raise TypeError("vectors of one expression must share a dtype (%s and %s)" % (ref.dtype, t.dtype))
-                if t.numel() != ref.numel():
-                    raise ValueError("vectors of one expression must have one length (%d and %d)"
-                                     % (ref.numel(), t.numel()))
-                if t.device != ref.device:
+                ref = self._keys[0]
+                if key[2] != ref[2]:
+                    raise TypeError("vectors of one expression must share a dtype (%s and %s)" % (ref[2], key[2]))
+                if key[1] != ref[1]:
+                    raise ValueError("vectors of one expression must have one length (%d and %d)" % (ref[1], key[1]))
+                if key[3] != ref[3]:
                     raise ValueError("vectors of one expression must be on one device")
             if len(self.operands) == S.MAX_OPERANDS:
                 raise ValueError("an expression reads at most %d distinct vectors" % S.MAX_OPERANDS)
-            self._ops[key] = len(self.operands)
+            k = self._ops[key] = len(self.operands)
             self.operands.append(t)
-        return self._ops[key]
+            self._keys.append(key)
+        self._seen[id(t)] = k
+        return k
 
     def _scalar(self, s: Scalar) -> int:
         key = struct.pack("<d", s.value)  # by bits: -0.0 and 0.0 stay apart
         if key not in self._scs:
-            if len(self.scalars) == S.MAX_SCALARS:
+            if self.params + len(self.scalars) == S.MAX_SCALARS:
                 raise ValueError("an expression uses at most %d distinct scalars" % S.MAX_SCALARS)
-            self._scs[key] = len(self.scalars)
+            self._scs[key] = self.params + len(self.scalars)
             self.scalars.append(s.value)
         return self._scs[key]
 
-    def _emit(self, root: Expr, limit: int) -> list:
-        swap = _need(root, False, {}) > limit
-        memo = {} if swap else None
+    def _emit(self, root: Expr, memo) -> list:
+        """Postfix of `root`: left operand first, or (memo a dict) with the
+        side that needs more stack first in additions and multiplications.
+        Stops as soon as the tree is too large: past MAX_TOKENS tokens, or
+        nested deeper than a tree of MAX_TOKENS tokens can be."""
         out = []
+        cap = S.MAX_TOKENS
 
-        def walk(e):
+        def too_large():
+            return ValueError("an expression expands to more than %d tokens" % cap)
+
+        def walk(e, depth):
             if isinstance(e, Vec):
                 out.append(S.token(S.LOAD, self._operand(e)))
             elif isinstance(e, Scalar):
                 out.append(S.token(S.SCALAR, self._scalar(e)))
+            elif isinstance(e, Param):
+                out.append(S.token(S.SCALAR if e.scalar else S.LOAD, e.slot))
             else:
+                if 2 * depth + 3 > cap:  # this node, a leaf beside each ancestor
+                    raise too_large()
                 first, second = e.left, e.right
-                if swap and e.op != S.SUB and _need(second, True, memo) > _need(first, True, memo):
+                if memo is not None and e.op != S.SUB and _need(second, True, memo) > _need(first, True, memo):
                     first, second = second, first
-                walk(first)
-                walk(second)
+                walk(first, depth + 1)
+                walk(second, depth + 1)
                 out.append(S.token(e.op))
+            if len(out) > cap:
+                raise too_large()
 
-        walk(root)
+        walk(root, 0)
         return out
 
     def add(self, root: Expr, limit: int = None) -> list:
+        """Tokens of one tree (as written; reordered when that needs more
+        than `limit` stack slots, MAX_STACK by default)."""
         root = _as_expr(root)
-        if _count_nodes([root], S.MAX_TOKENS) > S.MAX_TOKENS:
-            raise ValueError("an expression expands to more than %d tokens" % S.MAX_TOKENS)
-        return self._emit(root, S.MAX_STACK if limit is None else limit)
+        tokens = self._emit(root, None)
+        if stack_need(tokens) > (S.MAX_STACK if limit is None else limit):
+            tokens = self._emit(root, {})
+        return tokens
 
     def check_output(self, out) -> None:
         if out.dim() != 1 or (out.numel() > 1 and out.stride(0) != 1):
@@ -290,7 +330,7 @@ def program(expr, expr2=None) -> Program:
     return p
 
 
-def pair_program(x, y) -> Program:
+def pair_program(x, y, params: int | None = None) -> Program:
     """The programs of dot(x, y) over one operand list. One of the two must
     leave a stack slot for the other's value: the trees as written, else the
     first and then the second held to one slot less (by exchanging operands
@@ -299,6 +339,8 @@ def pair_program(x, y) -> Program:
     x, y = _as_expr(x), _as_expr(y)
     for lx, ly in ((None, None), (S.MAX_STACK - 1, None), (None, S.MAX_STACK - 1)):
         p = Program()
+        if params is not None:
+            p.template, p.params = True, params
         p.tokens = p.add(x, lx)
         p.tokens2 = p.add(y, ly)
         if min(stack_need(p.tokens), stack_need(p.tokens2)) < S.MAX_STACK:
@@ -329,3 +371,100 @@ def norm(x, stream=None, result=None):
     if not p.operands:
         raise ValueError("the norm of scalars only has no length")
     return S.salt_nrm2_expr(p.tokens, p.operands, p.scalars, result=result, stream=stream)
+
+
+class expression:
+    """A tree built once, from a function of its parameters, and evaluated
+    by each call: the counterpart of the paper's compile-time expression
+    types (Sec. 2). The tree, its postfix program and its scalar literals are
+    fixed when the object is made; a call only hands the library its
+    vectors, scalars and output, so its host cost is that of one salt_eval
+    call whatever the tree's size.
+
+    The function's parameters named in `scalars` are numbers, the others
+    vectors (1-D GPU tensors or Vec, one element type and length per call).
+    A function returning one tree evaluates into an output or takes its
+    norm; one returning a pair (x, y) takes their dot product::
+
+        fig1 = expression(lambda a, b, c: a + (b - c))
+        fig1(d, ta, tb, tc)                      # d <- a + (b - c)
+        axpy = expression(lambda x, y, alpha: alpha * x + y, scalars=("alpha",))
+        axpy(ty, tx, ty, 2.5)                    # in place
+        pair = expression(lambda a, b: (a + b, a - b))
+        r = pair.dot(ta, tb)                     # device scalar
+    """
+
+    def __init__(self, fn, scalars: Sequence[str] = ()):
+        import inspect
+
+        names = list(inspect.signature(fn).parameters)
+        unknown = set(scalars) - set(names)
+        if unknown:
+            raise ValueError("scalars names no parameter: %s" % sorted(unknown))
+        self.names = names
+        self.is_scalar = [n in scalars for n in names]
+        nv = sum(1 for x in self.is_scalar if not x)
+        ns = len(names) - nv
+        if nv > S.MAX_OPERANDS or ns > S.MAX_SCALARS:
+            raise ValueError("at most %d vector and %d scalar parameters" % (S.MAX_OPERANDS, S.MAX_SCALARS))
+        slots, kv, ks = [], 0, 0
+        for sc, n in zip(self.is_scalar, names):
+            slots.append(Param(ks if sc else kv, sc, n))
+            ks, kv = ks + sc, kv + (not sc)
+        tree = fn(*slots)
+        if isinstance(tree, tuple):
+            if len(tree) != 2:
+                raise ValueError("a dot product takes a pair of trees")
+            p = pair_program(tree[0], tree[1], params=ns)
+            self.pair = True
+        else:
+            p = Program()
+            p.template, p.params = True, ns
+            p.tokens = p.add(_as_expr(tree))
+            self.pair = False
+        self.tokens, self.tokens2, self.literals = p.tokens, p.tokens2, list(p.scalars)
+        self.tree = tree
+
+    def _split(self, args):
+        if len(args) != len(self.names):
+            raise TypeError("expected %d arguments (%s), got %d" % (len(self.names), ", ".join(self.names), len(args)))
+        vecs, scs = [], []
+        for sc, a in zip(self.is_scalar, args):
+            if sc:
+                scs.append(float(a))
+            else:
+                vecs.append(a.tensor if isinstance(a, Vec) else a)
+        n = vecs[0].numel() if vecs else None
+        for t in vecs:
+            if t.numel() != n:
+                raise ValueError("vectors of one call must have one length (%d and %d)" % (n, t.numel()))
+        return vecs, scs + self.literals, n
+
+    def __call__(self, out, *args, stream=None):
+        """out <- the tree over these arguments, in one salt_eval call."""
+        if self.pair:
+            raise TypeError("a pair of trees has no single value: use .dot(...)")
+        out = out.tensor if isinstance(out, Vec) else out
+        vecs, scs, n = self._split(args)
+        if n is not None and out.numel() != n:
+            raise ValueError("output length %d differs from the vectors' %d" % (out.numel(), n))
+        S.salt_eval(self.tokens, vecs, scs, out, n=out.numel(), stream=stream)
+        return out
+
+    def dot(self, *args, stream=None, result=None):
+        """Device scalar sum_i x_i * y_i of the pair (one salt_dot_expr call)."""
+        if not self.pair:
+            raise TypeError("a dot product needs a function returning a pair (x, y)")
+        vecs, scs, n = self._split(args)
+        if n is None:
+            raise ValueError("a dot product of scalars only has no length")
+        return S.salt_dot_expr(self.tokens, self.tokens2, vecs, scs, n=n, result=result, stream=stream)
+
+    def norm(self, *args, stream=None, result=None):
+        """Device scalar sqrt(sum_i x_i^2) of the tree (one salt_nrm2_expr call)."""
+        if self.pair:
+            raise TypeError("the norm takes one tree")
+        vecs, scs, n = self._split(args)
+        if n is None:
+            raise ValueError("the norm of scalars only has no length")
+        return S.salt_nrm2_expr(self.tokens, vecs, scs, n=n, result=result, stream=stream)

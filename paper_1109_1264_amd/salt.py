@@ -154,28 +154,45 @@ def check(status: int) -> None:
         raise SaltError(status, lib().salt_last_error().decode())
 
 
+_PROGS = {}  # token tuple -> (ctypes array, length); the library only reads it
+
+
 def _prog(tokens: Sequence[int]):
-    arr = (ctypes.c_uint32 * max(1, len(tokens)))(*[int(t) & 0xFFFFFFFF for t in tokens])
-    return arr, len(tokens)
+    key = tuple(tokens)
+    hit = _PROGS.get(key)
+    if hit is None:
+        if len(_PROGS) >= 4096:
+            _PROGS.clear()
+        hit = ((ctypes.c_uint32 * max(1, len(key)))(*[int(t) & 0xFFFFFFFF for t in key]), len(key))
+        _PROGS[key] = hit
+    return hit
 
 
 # ---------------------------------------------------------------------------
 # torch plumbing (device memory and streams only)
 # ---------------------------------------------------------------------------
 
-def dtype_code(t) -> int:
-    import torch
+_CODES = {}
 
-    m = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
-    if t.dtype not in m:
+
+def dtype_code(t) -> int:
+    if not _CODES:
+        import torch
+
+        _CODES.update({torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16})
+    c = _CODES.get(t.dtype)
+    if c is None:
         raise TypeError("unsupported tensor dtype %s" % t.dtype)
-    return m[t.dtype]
+    return c
 
 
 def _stream_ptr(stream) -> int:
     import torch
 
     if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:  # the current stream's handle without a Stream object
+            return int(raw(torch._C._cuda_getDevice()))
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
@@ -200,16 +217,19 @@ def salt_eval(prog: Sequence[int], operands, scalars, out, n: int | None = None,
               stream=None, config=None) -> None:
     """out[i] = prog(operands[...][i]; scalars) on the GPU (see salt.h)."""
     d = dtype_code(out)
+    if n is None:
+        n = out.numel()
+    if out.numel() < n:
+        raise ValueError("tensor shorter than n")
+    ptrs = []
     for t in operands:
         if dtype_code(t) != d:
             raise TypeError("all operands must have the output's dtype")
-    if n is None:
-        n = out.numel()
-    for t in list(operands) + [out]:
         if t.numel() < n:
             raise ValueError("tensor shorter than n")
+        ptrs.append(_dev(t))
     parr, plen = _prog(prog)
-    ops = (ctypes.c_void_p * max(1, len(operands)))(*[_dev(t) for t in operands])
+    ops = (ctypes.c_void_p * max(1, len(ptrs)))(*ptrs)
     sc = (ctypes.c_double * max(1, len(scalars)))(*[float(s) for s in scalars])
     L = lib()
     if config is None:

@@ -16,7 +16,8 @@ import torch
 import oracle
 from paper_1109_1264_amd import salt as S
 from paper_1109_1264_amd import workloads
-from paper_1109_1264_amd.expr import Node, Scalar, Vec, dot, norm, pair_program, program, stack_need
+from paper_1109_1264_amd.expr import (Node, Scalar, Vec, dot, expression, norm, operand_key, pair_program,
+                                      program, stack_need)
 
 T = S.token
 
@@ -135,8 +136,7 @@ def natural_tokens(ex, p):
 
     def walk(e):
         if isinstance(e, Vec):
-            key = (e.tensor.data_ptr(), e.tensor.numel(), e.tensor.dtype, str(e.tensor.device))
-            out.append(T(S.LOAD, p._ops[key]))
+            out.append(T(S.LOAD, p._ops[operand_key(e.tensor)]))
         elif isinstance(e, Scalar):
             out.append(T(S.SCALAR, p.scalars.index(e.value)))
         else:
@@ -207,3 +207,53 @@ def test_dot_pairs_leave_a_slot_for_the_other_value():
     p = pair_program(v[0] + v[1], v[0] - v[1])
     assert p.tokens == [T(S.LOAD, 0), T(S.LOAD, 1), T(S.ADD)]
     assert p.tokens2 == [T(S.LOAD, 0), T(S.LOAD, 1), T(S.SUB)]
+
+
+def test_expressions_built_once():
+    """expression(fn): the tree of a function of placeholder parameters,
+    built once. Vector parameters load by position, scalar parameters come
+    first among the scalars and the literals after them; the catalogue trees
+    give the catalogue's token streams."""
+    cat = dict(S.salt_catalogue())
+    assert expression(lambda a, b, c: a + (b - c)).tokens == cat["fig1"]
+    assert expression(lambda a, b, c, e, f: a * b + c * e - f).tokens == cat["tree5"]
+    ax = expression(lambda x, y, alpha: alpha * x + y, scalars=("alpha",))
+    assert ax.tokens == cat["axpy"] and ax.literals == [] and ax.is_scalar == [False, False, True]
+    # literals are numbered after the scalar parameters; parameter order is
+    # the load order whatever the order of use
+    g = expression(lambda b, a, s: (a - b) * s + 0.5 * a - 0.5, scalars=("s",))
+    assert g.tokens == [T(S.LOAD, 1), T(S.LOAD, 0), T(S.SUB), T(S.SCALAR, 0), T(S.MUL), T(S.SCALAR, 1),
+                        T(S.LOAD, 1), T(S.MUL), T(S.ADD), T(S.SCALAR, 1), T(S.SUB)]
+    assert g.literals == [0.5]
+    S.salt_program_check(g.tokens, 2, 1 + len(g.literals))
+    pair = expression(lambda a, b: (a + b, a - b))
+    assert pair.pair and pair.tokens == [T(S.LOAD, 0), T(S.LOAD, 1), T(S.ADD)]
+    assert pair.tokens2 == [T(S.LOAD, 0), T(S.LOAD, 1), T(S.SUB)]
+    assert S.salt_reduce_expr_route(pair.tokens, pair.tokens2, 2, 0) == 0     # the catalogue pair
+    # a deep tree is reordered as in the operator form
+    deep = expression(lambda a, b: a + (b + (a + (b + (a + (b + (a + (b + (a + b)))))))))
+    assert stack_need(deep.tokens) <= S.MAX_STACK
+    # errors, all before anything runs
+    with pytest.raises(ValueError):
+        expression(lambda a: a * 2, scalars=("alpha",))                  # no such parameter
+    with pytest.raises(ValueError):
+        expression(lambda a, b, c: (a, b, c))                             # three trees
+    x = Vec(torch.zeros(8, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        expression(lambda a: a + x)                                       # a captured vector
+    with pytest.raises(ValueError):
+        expression(lambda a0, a1, a2, a3, a4, a5, a6, a7, a8: a0)         # nine vector parameters
+    fig1 = expression(lambda a, b, c: a + (b - c))
+    t = [torch.zeros(8, dtype=torch.float64) for _ in range(3)]
+    with pytest.raises(TypeError):
+        fig1(t[0], t[0], t[1])                                            # too few arguments
+    with pytest.raises(ValueError):
+        fig1(t[0], t[0], t[1], torch.zeros(9, dtype=torch.float64))      # two lengths
+    with pytest.raises(ValueError):
+        fig1(torch.zeros(9, dtype=torch.float64), *t)                    # output length
+    with pytest.raises(TypeError):
+        fig1.dot(*t)                                                      # not a pair
+    with pytest.raises(TypeError):
+        pair(t[0], t[1], t[2])                                            # a pair has no single value
+    with pytest.raises(TypeError):
+        pair.norm(t[0], t[1])

@@ -13,7 +13,7 @@ import pytest
 import oracle
 from paper_1109_1264_amd import salt as S
 from paper_1109_1264_amd import workloads
-from paper_1109_1264_amd.expr import Node, Scalar, Vec, dot, norm, program, stack_need
+from paper_1109_1264_amd.expr import Node, Scalar, Vec, dot, expression, norm, operand_key, program, stack_need
 from tests.gpu_util import BITS, CODE, first_mismatch, to_dev, to_host_bits
 
 pytestmark = pytest.mark.gpu
@@ -27,18 +27,13 @@ def leaves(dtype, n, seed, count, offset=0):
     return host, [Vec(to_dev(h, dtype, offset=offset)) for h in host]
 
 
-def key(t):
-    # how the front end tells vectors apart (two empty vectors are one)
-    return (t.data_ptr(), t.numel(), t.dtype, str(t.device))
-
-
 def natural(ex, p):
     """Left-first postfix of `ex` in p's numbering (the tree as written)."""
     out = []
 
     def walk(e):
         if isinstance(e, Vec):
-            out.append(T(S.LOAD, next(k for k, t in enumerate(p.operands) if key(t) == key(e.tensor))))
+            out.append(T(S.LOAD, next(k for k, t in enumerate(p.operands) if operand_key(t) == operand_key(e.tensor))))
         elif isinstance(e, Scalar):
             out.append(T(S.SCALAR, p.scalars.index(e.value)))
         else:
@@ -151,3 +146,35 @@ def test_dot_and_norm_of_expressions(dtype):
                 vy = oracle.widen(oracle_of(y, host_of, dtype, n), dtype)
                 ref, abs_sum = oracle.dot2(vx, vy)
                 assert abs(got.item() - ref) <= oracle.TOL[dtype] * abs_sum + 1e-300, (name, n)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_expressions_built_once(dtype):
+    """A tree built once by expression() and called with several argument
+    sets has, every time, the bits of the same tree written with operators
+    (checked against the oracle); its dot and norm have the bits of the
+    operator forms."""
+    import torch
+
+    host, vs = leaves(dtype, N, 555, 3, offset=1)
+    host_of = {id(v.tensor): h for v, h in zip(vs, host)}
+    a, b, c = vs
+    f = expression(lambda x, y, z, s: (x - y) * s + z * 0.75, scalars=("s",))
+    out = Vec(to_dev(np.zeros_like(host[0]), dtype))
+    for (x, y, z), s in (((a, b, c), 1.375), ((c, a, b), -2.5), ((b, b, a), 0.0)):
+        print("case", dtype, s, flush=True)
+        f(out, x.tensor, y, z.tensor, s)              # tensors or Vec
+        torch.cuda.synchronize()
+        check_bits(out.tensor, oracle_of((x - y) * s + z * 0.75, host_of, dtype, N), dtype, ("template", s))
+    pair = expression(lambda x, y: (x + y, x - y))
+    got = pair.dot(a, b)
+    want = dot(a + b, a - b)
+    nrm = f.norm(a, b, c, 1.375)
+    want_nrm = norm((a - b) * 1.375 + c * 0.75)
+    torch.cuda.synchronize()
+    assert got.item() == want.item(), (got.item(), want.item())
+    assert nrm.item() == want_nrm.item(), (nrm.item(), want_nrm.item())
+    vx = oracle.widen(oracle_of(a + b, host_of, dtype, N), dtype)
+    vy = oracle.widen(oracle_of(a - b, host_of, dtype, N), dtype)
+    ref, abs_sum = oracle.dot2(vx, vy)
+    assert abs(got.item() - ref) <= oracle.TOL[dtype] * abs_sum
