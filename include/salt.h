@@ -24,6 +24,12 @@
  *    enqueued, with no partial effect. A failed launch returns
  *    SALT_ERR_DEVICE. No C++ exception crosses this interface.
  *    salt_last_error() gives a thread-local message for the last failure.
+ *  - Calls may come from several host threads at once: the library's own
+ *    state (the tuning table, the cache of run-time compiled kernels) is
+ *    guarded, and calls on different streams may run concurrently on the
+ *    device. A caller's buffers are its own to order: two calls that write
+ *    the same output or workspace on unordered streams race (as do
+ *    overlapping salt_dot_noalloc calls, which share the library's buffer).
  *  - Any element alignment is accepted; 16-byte aligned arrays take the
  *    vectorised (16 B per lane) path, others a per-element path with the
  *    same results (the paper's non-specialised fallback loop, Sec. 4.2).
