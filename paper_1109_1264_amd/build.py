@@ -43,6 +43,11 @@ JIT_HEADERS = [os.path.join(INCLUDE, "salt.h")] + [
                                     "reduce_tree.hpp", "batch.hpp", "batch_device.hpp")]
 JIT_HEADERS_INC = os.path.join(BUILD_DIR, "jit_headers.inc")
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
+# A plain C program using the library through include/salt.h alone (no
+# Python, no torch), built next to the library.
+EXAMPLE_SRC = os.path.join(PKG, "examples", "fig1_dot.c")
+EXAMPLE = os.path.join(PKG, "fig1_dot")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
 def _hipcc() -> str:
@@ -103,7 +108,19 @@ def build(verbose: bool = False) -> str:
     _run([_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp,
           *[o for _, o in jobs], "-ldl", "-lhiprtc"])
     os.replace(tmp, LIB)
+    build_example()
     return LIB
+
+
+def build_example() -> str:
+    """Compile examples/fig1_dot.c as C against the installed library and
+    the HIP runtime; returns the program's path."""
+    tmp = EXAMPLE + ".tmp%d" % os.getpid()
+    _run(["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include"),
+          "-I" + INCLUDE, "-o", tmp, EXAMPLE_SRC, "-L" + PKG, "-lsalt", "-L" + os.path.join(ROCM, "lib"),
+          "-lamdhip64", "-Wl,-rpath,$ORIGIN:" + os.path.join(ROCM, "lib")])
+    os.replace(tmp, EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":
