@@ -165,21 +165,29 @@ class Node(Expr):
         return "(%r %s %r)" % (self.left, _SYMBOL[self.op], self.right)
 
 
-def _as_expr(x) -> Expr:
+def _leaf(x):
+    """x as a tree node, or None for a type that takes no part in trees."""
     if isinstance(x, Expr):
         return x
     if isinstance(x, numbers.Real) and not isinstance(x, bool):
         return Scalar(x)
     if hasattr(x, "data_ptr") and hasattr(x, "dim"):
-        return Vec(x)
-    raise TypeError("cannot use %s in a vector expression" % type(x).__name__)
+        return Vec(x)  # raises for a tensor the library cannot take
+    return None
+
+
+def _as_expr(x) -> Expr:
+    e = _leaf(x)
+    if e is None:
+        raise TypeError("cannot use %s in a vector expression" % type(x).__name__)
+    return e
 
 
 def _node(op, left, right):
-    try:
-        return Node(op, _as_expr(left), _as_expr(right))
-    except TypeError:
-        return NotImplemented
+    l, r = _leaf(left), _leaf(right)
+    if l is None or r is None:
+        return NotImplemented  # Python then tries the other operand, or raises TypeError
+    return Node(op, l, r)
 
 
 def _need(e: Expr, swap: bool, memo: dict) -> int:

@@ -102,6 +102,10 @@ def test_limits_and_errors_before_any_launch():
         Vec(torch.zeros(8, dtype=torch.float64)[::2])              # not unit stride
     with pytest.raises(TypeError):
         Vec(torch.zeros(8, dtype=torch.int32))                      # no such element type
+    with pytest.raises(TypeError, match="unsupported tensor dtype"):
+        a + torch.zeros(16, dtype=torch.int32)                      # the tensor's own error, not a generic one
+    with pytest.raises(ValueError, match="1-D"):
+        a + torch.zeros(4, 4, dtype=torch.float64)
     with pytest.raises(TypeError):
         a / b                                                       # not an operation of the method
     with pytest.raises(TypeError):
