@@ -468,6 +468,37 @@ class expression:
             raise ValueError("a dot product of scalars only has no length")
         return S.salt_dot_expr(self.tokens, self.tokens2, vecs, scs, n=n, result=result, stream=stream)
 
+    def batch(self, items, dots=None, stream=None):
+        """Many evaluations of this tree in one persistent launch: a batched
+        plan (paper_1109_1264_amd.batch.Batch; launch it, or capture it in a
+        graph) whose item k is items[k] = (out, *args), as for a call. The
+        items may differ in length, vectors and scalars, not in element
+        type. With `dots`, item k also computes into dots[k] (a one-element
+        device tensor, or None) the dot product of the first two vectors
+        the tree reads, in the same pass, with the bits of salt_dot on them."""
+        from .batch import Batch
+
+        if self.pair:
+            raise TypeError("a batch evaluates one tree per item")
+        if not items:
+            raise ValueError("a batch needs at least one item")
+        if dots is not None and len(dots) != len(items):
+            raise ValueError("one dot result (or None) per item")
+        plan, dtype = [], None
+        for k, item in enumerate(items):
+            out = item[0].tensor if isinstance(item[0], Vec) else item[0]
+            vecs, scs, n = self._split(item[1:])
+            if n is not None and out.numel() != n:
+                raise ValueError("item %d: output length %d differs from the vectors' %d" % (k, out.numel(), n))
+            d = S.dtype_code(out)
+            if dtype is None:
+                dtype = d
+            elif d != dtype:
+                raise TypeError("the items of one batch share an element type")
+            plan.append({"n": out.numel(), "operands": vecs, "scalars": scs, "out": out,
+                         "dot_out": None if dots is None else dots[k]})
+        return Batch(self.tokens, plan, dtype, stream=stream)
+
     def norm(self, *args, stream=None, result=None):
         """Device scalar sqrt(sum_i x_i^2) of the tree (one salt_nrm2_expr call)."""
         if self.pair:

@@ -261,3 +261,23 @@ def test_expressions_built_once():
         pair(t[0], t[1], t[2])                                            # a pair has no single value
     with pytest.raises(TypeError):
         pair.norm(t[0], t[1])
+
+
+def test_expression_batches_check_their_items_first():
+    """expression(...).batch: a pair cannot be batched; an empty list, a
+    dots list of the wrong length, two element types or a wrong output
+    length are refused before any plan is made."""
+    f = expression(lambda a, b: a - b)
+    pair = expression(lambda a, b: (a + b, a - b))
+    t64 = [torch.zeros(8, dtype=torch.float64) for _ in range(3)]
+    t32 = [torch.zeros(8, dtype=torch.float32) for _ in range(3)]
+    with pytest.raises(TypeError):
+        pair.batch([(t64[0], t64[1], t64[2])])
+    with pytest.raises(ValueError):
+        f.batch([])
+    with pytest.raises(ValueError):
+        f.batch([(t64[0], t64[1], t64[2])], dots=[None, None])
+    with pytest.raises(TypeError):
+        f.batch([(t64[0], t64[1], t64[2]), (t32[0], t32[1], t32[2])])
+    with pytest.raises(ValueError):
+        f.batch([(torch.zeros(9, dtype=torch.float64), t64[1], t64[2])])

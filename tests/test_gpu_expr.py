@@ -178,3 +178,52 @@ def test_expressions_built_once(dtype):
     vy = oracle.widen(oracle_of(a - b, host_of, dtype, N), dtype)
     ref, abs_sum = oracle.dot2(vx, vy)
     assert abs(got.item() - ref) <= oracle.TOL[dtype] * abs_sum
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_expression_batch(dtype):
+    """A built-once tree over 26 ragged items (aligned and not, each with its
+    own scalar) as one batched launch and as a replayed graph: every output
+    has the bits of the oracle evaluating the tree as written, and the fused
+    dots those of salt_dot on the two vectors the tree reads first."""
+    import torch
+
+    rng = np.random.default_rng(77)
+    f = expression(lambda x, y, z, s: (x - y) * s + z * 0.75, scalars=("s",))
+    lengths = [1, 5, 100, 4099, 16387, 70001] + [int(v) for v in rng.integers(1, 40000, 20)]
+    rdt = torch.float64 if dtype == "f64" else torch.float32
+    items, dots, cases = [], [], []
+    for k, n in enumerate(lengths):
+        host = workloads.uniform(n, dtype, 6000 + k, 3)
+        vs = [Vec(to_dev(h, dtype, offset=k % 2)) for h in host]
+        out = to_dev(np.zeros_like(host[0]), dtype, offset=(k // 2) % 2)
+        s = float(rng.uniform(-2, 2))
+        items.append((out, vs[0], vs[1].tensor, vs[2], s))
+        dots.append(torch.empty(1, dtype=rdt, device="cuda") if k % 3 else None)
+        cases.append((host, vs, out, s))
+    b = f.batch(items, dots=dots)
+    b.launch()
+    torch.cuda.synchronize()
+
+    def check(tag):
+        for k, (host, vs, out, s) in enumerate(cases):
+            x, y, z = vs
+            host_of = {id(v.tensor): h for v, h in zip(vs, host)}
+            want = oracle_of((x - y) * s + z * 0.75, host_of, dtype, len(host[0]))
+            check_bits(out, want, dtype, (tag, k))
+            if dots[k] is not None:
+                alone = S.salt_dot(x.tensor, y.tensor)
+                torch.cuda.synchronize()
+                assert dots[k].item() == alone.item(), (tag, k, dots[k].item(), alone.item())
+
+    check("launch")
+    g = b.graph()
+    for _, _, out, _ in cases:
+        out.zero_()
+    for d in dots:
+        if d is not None:
+            d.zero_()
+    torch.cuda.synchronize()
+    g.launch()
+    torch.cuda.synchronize()
+    check("graph")
