@@ -474,8 +474,10 @@ class expression:
         graph) whose item k is items[k] = (out, *args), as for a call. The
         items may differ in length, vectors and scalars, not in element
         type. With `dots`, item k also computes into dots[k] (a one-element
-        device tensor, or None) the dot product of the first two vectors
-        the tree reads, in the same pass, with the bits of salt_dot on them."""
+        device tensor, or None) the dot product of its first two vector
+        arguments, in the same pass, with the bits of salt_dot on them; the
+        tree must read those two first, in that order (the plan refuses it
+        otherwise)."""
         from .batch import Batch
 
         if self.pair:

@@ -182,15 +182,16 @@ def test_expressions_built_once(dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_expression_batch(dtype):
-    """A built-once tree over 26 ragged items (aligned and not, each with its
+    """A built-once tree over 27 ragged items (aligned and not, each with its
     own scalar) as one batched launch and as a replayed graph: every output
     has the bits of the oracle evaluating the tree as written, and the fused
-    dots those of salt_dot on the two vectors the tree reads first."""
+    dots those of salt_dot on the first two vector arguments (which the
+    tree reads first). Empty items are part of the list."""
     import torch
 
     rng = np.random.default_rng(77)
     f = expression(lambda x, y, z, s: (x - y) * s + z * 0.75, scalars=("s",))
-    lengths = [1, 5, 100, 4099, 16387, 70001] + [int(v) for v in rng.integers(1, 40000, 20)]
+    lengths = [1, 0, 5, 100, 4099, 16387, 70001] + [int(v) for v in rng.integers(1, 40000, 20)]
     rdt = torch.float64 if dtype == "f64" else torch.float32
     items, dots, cases = [], [], []
     for k, n in enumerate(lengths):
@@ -227,3 +228,22 @@ def test_expression_batch(dtype):
     g.launch()
     torch.cuda.synchronize()
     check("graph")
+
+
+def test_expression_batch_dot_needs_its_first_two_vectors_read_first():
+    """A fused dot takes the first two vector arguments; a tree that reads
+    another vector first is refused when the plan is made."""
+    import torch
+
+    n = 1000
+    host = workloads.uniform(n, "f64", 31, 2)
+    x, y = (to_dev(h, "f64") for h in host)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    r = torch.empty(1, dtype=torch.float64, device="cuda")
+    swapped = expression(lambda a, b: b - a)
+    with pytest.raises(S.SaltError):
+        swapped.batch([(out, x, y)], dots=[r])
+    swapped.batch([(out, x, y)]).launch()          # without the dot it runs
+    torch.cuda.synchronize()
+    want = oracle.eval_program([T(S.LOAD, 1), T(S.LOAD, 0), T(S.SUB)], host, [], "f64")
+    check_bits(out, want, "f64", "swapped")
