@@ -21,7 +21,9 @@ step):
     sweep:     axpy, dot, nrm2 and the 5-operand tree for n = 2^10 .. 2^28 in
                binary64 and binary32 (device time per launch, GB/s, % of
                8 TB/s, % of the copy tree's rate at the same n, and whether
-               the working set is past the last-level cache);
+               the working set is past the last-level cache), and the host
+               time per small call of the binding and the expression front
+               end (host_enqueue_us);
     fusion:    one fused pass against the same result composed from
                single-operation calls (out-of-place scale, a + (b - c),
                dot of two trees), with identical bits; and the Fig. 1 tree
