@@ -44,8 +44,8 @@ from typing import Sequence
 
 from . import salt as S
 
-__all__ = ["Expr", "Vec", "Scalar", "Param", "Node", "expression", "Program", "program", "pair_program", "operand_key", "stack_need",
-           "dot", "norm"]
+__all__ = ["Expr", "Vec", "Scalar", "Param", "Node", "expression", "Program", "program", "pair_program",
+           "operand_key", "stack_need", "dot", "norm"]
 
 _SYMBOL = {S.ADD: "+", S.SUB: "-", S.MUL: "*"}
 
